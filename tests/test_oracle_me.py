@@ -1,0 +1,283 @@
+"""Pins for the oracle's matrix elements, cross sections and gradients (CPU only).
+
+* e+e- -> mu+mu-: e^4 (1 + cos^2 theta) per event; only 4 of 16 helicities contribute.
+* gg -> ttbar: LO closed form per event (explicit-colour and colour-ordered modes).
+* explicit colour (all Feynman diagrams, explicit SU(3) indices) == colour-ordered form.
+* gluon Ward identity (eps -> k) for every partial amplitude and the full amplitude.
+* Lorentz invariance under boosts and rotations; Bose symmetry; alpha_s scaling.
+* cross sections vs closed forms within the Monte Carlo error.
+* reverse-mode gradient vs central finite differences.
+* planted mistakes (a flipped vertex sign, a dropped mass term, a wrong colour
+  matrix, a wrong weight exponent) make one of the pins fail.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import (closed_forms, colour, grad, integrand, me_explicit, me_ordered,
+                    phase_space, philox, processes, vegas)
+from oracle.kinematics import general_boost, rotate
+
+P = processes.DEFAULT_PARAMS
+PEE = processes.EE_PARAMS
+
+
+def events(proc, N, seed, params=P):
+    d = processes.dims(proc)
+    u = torch.tensor(philox.uniforms(seed, N, d).T.copy())
+    p, w = integrand.momenta(proc, params, u)
+    return p
+
+
+def _angle_events(N, sqrt_s, m, seed=0):
+    g = torch.Generator().manual_seed(seed)
+    c = 2 * torch.rand(N, generator=g, dtype=torch.float64) - 1
+    ph = 2 * math.pi * torch.rand(N, generator=g, dtype=torch.float64)
+    E = sqrt_s / 2
+    q = math.sqrt(E * E - m * m)
+    s = torch.sqrt(1 - c * c)
+    p = torch.zeros(N, 4, 4, dtype=torch.float64)
+    p[:, 0] = torch.tensor([E, 0, 0, E])
+    p[:, 1] = torch.tensor([E, 0, 0, -E])
+    p[:, 2, 0] = E
+    p[:, 2, 1] = q * s * torch.cos(ph)
+    p[:, 2, 2] = q * s * torch.sin(ph)
+    p[:, 2, 3] = q * c
+    p[:, 3, 0] = E
+    p[:, 3, 1:] = -p[:, 2, 1:]
+    return p, c
+
+
+def test_ee_mumu_closed_form_per_event():
+    p, c = _angle_events(200, PEE['sqrt_s'], 0.0)
+    me = me_explicit.matrix_element('ee_mumu', p, PEE)
+    ref = torch.tensor([closed_forms.ee_mumu_me(float(x), PEE['alpha']) for x in c], dtype=torch.float64)
+    assert ((me / ref - 1).abs()).max() < 1e-12
+
+
+def test_ee_mumu_helicity_conservation():
+    p, _ = _angle_events(20, PEE['sqrt_s'], 0.0)
+    nz = 0
+    for h in processes.helicities('ee_mumu'):
+        a = me_explicit.amplitude_ee(p, h, PEE).abs().max()
+        if a > 1e-12:
+            nz += 1
+            assert h[0] == -h[1] and h[2] == -h[3]
+    assert nz == 4
+
+
+@pytest.mark.parametrize('mode', ['explicit', 'ordered'])
+def test_gg_tt_closed_form_per_event(mode):
+    p, c = _angle_events(200 if mode == 'ordered' else 50, P['sqrt_s'], P['m_t'], seed=1)
+    mod = me_explicit if mode == 'explicit' else me_ordered
+    me = mod.matrix_element('gg_tt', p, P)
+    ref = torch.tensor([closed_forms.gg_tt_me_costheta(float(x), P['sqrt_s'] ** 2, P['m_t'], P['alpha_s'])
+                        for x in c], dtype=torch.float64)
+    assert ((me / ref - 1).abs()).max() < 1e-12
+
+
+def test_gg_tt_closed_form_on_rambo_events():
+    p = events('gg_tt', 300, 2)
+    me = me_ordered.matrix_element('gg_tt', p, P)
+    s = P['sqrt_s'] ** 2
+    tau1 = 2 * (p[:, 0, 0] * p[:, 2, 0] - (p[:, 0, 1:] * p[:, 2, 1:]).sum(-1)) / s
+    ref = torch.tensor([closed_forms.gg_tt_me(float(t), s, P['m_t'], P['alpha_s']) for t in tau1],
+                       dtype=torch.float64)
+    assert ((me / ref - 1).abs()).max() < 1e-12
+
+
+@pytest.mark.parametrize('proc,N,hstep', [('gg_tt', 100, 1), ('gg_ttg', 20, 1), ('gg_ttgg', 2, 1)])
+def test_explicit_colour_equals_colour_ordered(proc, N, hstep):
+    p = events(proc, N, 3)
+    hels = processes.helicities(proc)[::hstep]
+    a = me_explicit.matrix_element(proc, p, P, hel_list=hels)
+    b = me_ordered.matrix_element(proc, p, P, hel_list=hels)
+    assert ((a / b - 1).abs()).max() < 1e-12
+
+
+def test_explicit_colour_equals_colour_ordered_ttgg_more_events():
+    p = events('gg_ttgg', 12, 4)
+    hels = processes.helicities('gg_ttgg')[3::9]
+    a = me_explicit.matrix_element('gg_ttgg', p, P, hel_list=hels)
+    b = me_ordered.matrix_element('gg_ttgg', p, P, hel_list=hels)
+    assert ((a / b - 1).abs()).max() < 1e-12
+
+
+@pytest.mark.parametrize('proc,N', [('gg_tt', 6), ('gg_ttg', 6), ('gg_ttgg', 3)])
+def test_ward_identity_partial_amplitudes(proc, N):
+    p = events(proc, N, 5)
+    k = processes.PROCESSES[proc]['n_ext'] - 2
+    hels = processes.helicities(proc)[::7]
+    # amplitude scale of this event sample (some helicities vanish identically)
+    scale = max(me_ordered.partial_amplitudes(p, h, P).abs().max() for h in hels) * P['sqrt_s']
+    for h in hels:
+        for j in range(k):
+            Aw = me_ordered.partial_amplitudes(p, h, P, ward=j)
+            assert Aw.abs().max() < 1e-13 * scale, (h, j)
+
+
+def test_ward_identity_explicit_colour_ttg():
+    p = events('gg_ttg', 3, 6)
+    hels = processes.helicities('gg_ttg')[::11]
+    scale = max(me_explicit.amplitude_qcd(p, h, P).abs().max() for h in hels) * P['sqrt_s']
+    for h in hels:
+        for j in range(3):
+            Mw = me_explicit.amplitude_qcd(p, h, P, ward=j)
+            assert Mw.abs().max() < 1e-13 * scale
+
+
+@pytest.mark.parametrize('proc,N', [('gg_tt', 50), ('gg_ttg', 20), ('gg_ttgg', 4)])
+def test_lorentz_invariance(proc, N):
+    p = events(proc, N, 7)
+    g = torch.Generator().manual_seed(11)
+    # random boost of rapidity <= 2 along a random axis, then a random rotation
+    y = 2 * torch.rand(N, generator=g, dtype=torch.float64)
+    axis = torch.randn(N, 3, generator=g, dtype=torch.float64)
+    axis = axis / axis.norm(dim=-1, keepdim=True)
+    beta = (torch.tanh(y).unsqueeze(-1) * axis).unsqueeze(1).expand(N, p.shape[1], 3)
+    pb = general_boost(p, beta)
+    Q, _ = torch.linalg.qr(torch.randn(3, 3, generator=g, dtype=torch.float64))
+    pb = rotate(pb, Q)
+    a = me_ordered.matrix_element(proc, p, P)
+    b = me_ordered.matrix_element(proc, pb, P)
+    assert ((a / b - 1).abs()).max() < 1e-12
+
+
+@pytest.mark.parametrize('proc,N', [('gg_tt', 30), ('gg_ttg', 10), ('gg_ttgg', 4)])
+def test_bose_symmetry(proc, N):
+    p = events(proc, N, 8)
+    a = me_ordered.matrix_element(proc, p, P)
+    q = p.clone()
+    q[:, [0, 1]] = p[:, [1, 0]]
+    assert ((me_ordered.matrix_element(proc, q, P) / a - 1).abs()).max() < 1e-12
+    if proc == 'gg_ttgg':
+        r = p.clone()
+        r[:, [4, 5]] = p[:, [5, 4]]
+        assert ((me_ordered.matrix_element(proc, r, P) / a - 1).abs()).max() < 1e-12
+
+
+@pytest.mark.parametrize('proc,k', [('gg_tt', 2), ('gg_ttg', 3), ('gg_ttgg', 4)])
+def test_alpha_s_scaling(proc, k):
+    p = events(proc, 5, 9)
+    a = me_ordered.matrix_element(proc, p, P)
+    P2 = dict(P, alpha_s=0.2)
+    b = me_ordered.matrix_element(proc, p, P2)
+    assert ((b / a - (0.2 / P['alpha_s']) ** k).abs() / (0.2 / P['alpha_s']) ** k).max() < 1e-13
+
+
+def test_ee_mumu_cross_section_within_sigma():
+    f = lambda y: integrand.integrand('ee_mumu', PEE, y)[0]
+    I, sig, chi2, _, _ = vegas.integrate(f, 2, 20000, 5, seed=1)
+    ref = closed_forms.ee_mumu_sigma(PEE['sqrt_s'] ** 2, PEE['alpha']) * closed_forms.GEV2_TO_PB
+    assert abs(I - ref) < 3 * sig
+    assert abs(ref - 8.690013) < 1e-5
+
+
+def test_gg_tt_cross_section_within_sigma():
+    f = lambda y: integrand.integrand('gg_tt', P, y)[0]
+    I, sig, chi2, _, _ = vegas.integrate(f, 2, 20000, 5, seed=2)
+    ref = closed_forms.gg_tt_sigma(P['sqrt_s'] ** 2, P['m_t'], P['alpha_s']) * closed_forms.GEV2_TO_PB
+    assert abs(I - ref) < 3 * sig
+
+
+def test_gg_tt_sigma_closed_form_vs_quadrature_of_me():
+    # the two published forms pin each other: integrate the per-event formula over cos theta
+    from scipy import integrate as si
+    s = P['sqrt_s'] ** 2
+    m = P['m_t']
+    beta = math.sqrt(1 - 4 * m * m / s)
+    f = lambda c: closed_forms.gg_tt_me_costheta(c, s, m, P['alpha_s'])
+    val = si.quad(f, -1, 1, epsabs=0, epsrel=1e-13)[0]
+    sigma = val * 2 * math.pi * beta / (32 * math.pi ** 2) / (2 * s)
+    assert abs(sigma / closed_forms.gg_tt_sigma(s, m, P['alpha_s']) - 1) < 1e-12
+
+
+@pytest.mark.parametrize('proc,N', [('gg_tt', 6), ('gg_ttg', 4)])
+def test_gradient_vs_finite_differences(proc, N):
+    d = processes.dims(proc)
+    x = 0.05 + 0.9 * philox.uniforms(13, N, d)
+    edges = vegas.uniform_grid(d, 50)
+    me, gx, gth = grad.vjp(proc, P, x, np.ones(N), edges)
+    fx, fm = grad.finite_difference(proc, P, x, edges)
+    assert np.abs(gx - fx).max() < 1e-6 * np.abs(fx).max()
+    assert np.abs(gth[:, 0] - fm).max() < 1e-6 * np.abs(fm).max()
+    k = processes.PROCESSES[proc]['n_ext'] - 2
+    assert np.allclose(gth[:, 1], k * me / P['alpha_s'], rtol=1e-14)
+
+
+def test_gradient_through_nonuniform_vegas_grid():
+    proc, N = 'gg_tt', 5
+    d = 2
+    rng = np.random.default_rng(3)
+    w = rng.uniform(0.5, 1.5, (d, 50))
+    edges = np.concatenate([np.zeros((d, 1)), np.cumsum(w, 1) / w.sum(1, keepdims=True)], 1)
+    # keep x away from bin boundaries so that x +- h stays in its bin
+    x = (np.floor(philox.uniforms(2, N, d) * 50) + 0.5) / 50
+    me, gx, gth = grad.vjp(proc, P, x, np.full(N, 2.0), edges)
+    fx, fm = grad.finite_difference(proc, P, x, edges)
+    assert np.abs(gx - 2 * fx).max() < 1e-6 * np.abs(2 * fx).max()
+
+
+# ---------------------------------------------------------------- planted mistakes
+
+def test_planted_vertex_sign_flip_breaks_closed_form(monkeypatch):
+    orig = me_ordered.K3
+    monkeypatch.setattr(me_ordered, 'K3', lambda *a: -orig(*a))
+    p, c = _angle_events(10, P['sqrt_s'], P['m_t'], seed=1)
+    me = me_ordered.matrix_element('gg_tt', p, P)
+    ref = torch.tensor([closed_forms.gg_tt_me_costheta(float(x), P['sqrt_s'] ** 2, P['m_t'], P['alpha_s'])
+                        for x in c], dtype=torch.float64)
+    assert ((me / ref - 1).abs()).max() > 1e-3
+
+
+def test_planted_four_gluon_sign_flip_breaks_ward_identity(monkeypatch):
+    orig = me_ordered.W4
+    monkeypatch.setattr(me_ordered, 'W4', lambda *a: -orig(*a))
+    p = events('gg_ttgg', 2, 5)
+    h = processes.helicities('gg_ttgg')[21]
+    A = me_ordered.partial_amplitudes(p, h, P)
+    Aw = me_ordered.partial_amplitudes(p, h, P, ward=3)
+    assert Aw.abs().max() > 1e-6 * A.abs().max() * P['sqrt_s']
+
+
+def test_planted_dropped_mass_term_breaks_closed_form(monkeypatch):
+    orig = me_ordered.pslash
+    p, c = _angle_events(10, P['sqrt_s'], P['m_t'], seed=2)
+    ref = torch.tensor([closed_forms.gg_tt_me_costheta(float(x), P['sqrt_s'] ** 2, P['m_t'], P['alpha_s'])
+                        for x in c], dtype=torch.float64)
+    # massless numerator in the propagator only: replace m by 0 after the spinors are built
+    real_eye = torch.eye
+
+    def fake_eye(n, **kw):
+        e = real_eye(n, **kw)
+        return e * 0 if n == 4 else e
+    monkeypatch.setattr(me_ordered.torch, 'eye', fake_eye)
+    me = me_ordered.matrix_element('gg_tt', p, P)
+    assert ((me / ref - 1).abs()).max() > 1e-3
+
+
+def test_planted_wrong_colour_matrix_breaks_explicit_comparison(monkeypatch):
+    C = me_ordered._CMAT[3].clone()
+    C[0, 1] = C[1, 0] = -C[0, 1]
+    monkeypatch.setitem(me_ordered._CMAT, 3, C)
+    p = events('gg_ttg', 3, 3)
+    hels = processes.helicities('gg_ttg')[::4]
+    a = me_explicit.matrix_element('gg_ttg', p, P, hel_list=hels)
+    b = me_ordered.matrix_element('gg_ttg', p, P, hel_list=hels)
+    assert ((a / b - 1).abs()).max() > 1e-6
+
+
+def test_planted_weight_exponent_breaks_two_body_pin(monkeypatch):
+    orig = phase_space.massive_rescale
+
+    def bad(p, masses, sqrt_s):
+        k, fac = orig(p, masses, sqrt_s)
+        kabs = torch.sqrt((k[..., 1:] ** 2).sum(-1))
+        return k, fac * (kabs.sum(-1) / sqrt_s)     # exponent 2n-2 instead of 2n-3
+    monkeypatch.setattr(phase_space, 'massive_rescale', bad)
+    u = torch.tensor(philox.uniforms(4, 100, 2).T.copy())
+    _, w = phase_space.phase_space(u, 1000.0, [173.0, 173.0])
+    beta = math.sqrt(1 - 4 * 173.0 ** 2 / 1e6)
+    assert (w / (beta / (8 * math.pi)) - 1).abs().max() > 1e-3
