@@ -1,0 +1,179 @@
+/*
+ * mf.h -- C ABI of the MI355X (gfx950) event-parallel matrix-element library.
+ *
+ * The library evaluates, for batches of Monte Carlo events, the hot path of
+ * an event-parallel tree-level generator: phase-space sampling, the
+ * spin/colour summed matrix element |M|^2, its derivative, and Vegas grid
+ * adaptation.  It corresponds to the custom operator of Carrazza,
+ * Cruz-Martinez, Palazzo, "Extending MadFlow: device-specific optimization"
+ * (ICHEP 2022): a momentum tensor in, a matrix-element tensor out, launched
+ * from a C++ host interface and wrapped for Python (sect. 2, Fig. 2); the
+ * derivative the paper left out (sect. 2) is provided by
+ * mf_matrix_element_vjp.  Monte Carlo integration is Vegas (sect. 1).
+ *
+ * Conventions for every entry point
+ *  - All array arguments are DEVICE pointers owned by the caller (for
+ *    example torch tensors); the library never frees them.  Argument structs
+ *    (mf_params, mf_request) are host memory read during the call only.
+ *  - Work is enqueued asynchronously on `stream` (a hipStream_t; NULL is the
+ *    default stream).  The status return covers argument validation and
+ *    launch errors only; mf_last_error() then gives a message (thread-local).
+ *  - Layouts are structure-of-arrays with the event index fastest.
+ *    Momenta: p[leg][component][event], component = (E, px, py, pz), legs in
+ *    the order of the process (incoming first), FP64.
+ *  - n = 0 is a valid no-op (returns MF_OK) except where stated.
+ *  - Numerical trouble is not an error: NaN inputs give NaN outputs; an
+ *    event whose massive phase-space rescaling does not converge gets
+ *    weight 0 and is counted (mf_failures).
+ */
+#ifndef MF_H
+#define MF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MF_OK = 0,
+    MF_ERR_INVALID_ARG = -1,  /* null pointer, negative size, unknown enum, ... */
+    MF_ERR_UNSUPPORTED = -2,  /* valid request this build cannot serve */
+    MF_ERR_HIP = -3,          /* HIP runtime error (message has the HIP error string) */
+    MF_ERR_NO_MEMORY = -4     /* workspace allocation failed */
+} mf_status;
+
+/* Processes (legs in momentum-array order):
+ *   MF_EE_MUMU : e-(in) e+(in) -> mu-(out) mu+(out), s-channel photon, massless
+ *   MF_GG_TT   : g g -> t tbar
+ *   MF_GG_TTG  : g g -> t tbar g
+ *   MF_GG_TTGG : g g -> t tbar g g
+ * The gg processes are the gluon-initiated channels of the paper's
+ * benchmarks (pp -> t tbar (+ g, + g g); sect. 3, Table 1, Figs. 3 and 4). */
+typedef enum { MF_EE_MUMU = 0, MF_GG_TT = 1, MF_GG_TTG = 2, MF_GG_TTGG = 3 } mf_process;
+
+/* Arithmetic of the matrix element.
+ *   MF_FP64           : everything in FP64; output f64.
+ *   MF_FP32           : FP64 kinematics, FP32 complex amplitudes, FP32 colour sum; output f32.
+ *   MF_FP32_MFMA_BF16 : as MF_FP32 with the colour contraction on BF16 matrix cores
+ *                       (colour matrix exact in BF16, amplitudes split in three BF16
+ *                       terms, FP32 accumulation); output f32.
+ *   MF_FP32_MFMA_F32  : as MF_FP32 with the colour contraction on FP32 matrix cores. */
+typedef enum { MF_FP64 = 0, MF_FP32 = 1, MF_FP32_MFMA_BF16 = 2, MF_FP32_MFMA_F32 = 3 } mf_precision;
+
+/* Physics and generation-cut parameters (GeV units).  alpha is used by
+ * MF_EE_MUMU only, m_t / alpha_s / cuts by the gg processes.  Cuts apply to
+ * final-state gluons: pT > pt_min, |eta| < eta_max, and Delta R > dr_min
+ * between the two final gluons of MF_GG_TTGG. */
+typedef struct {
+    double sqrt_s, m_t, alpha_s, alpha, pt_min, eta_max, dr_min;
+} mf_params;
+
+/* One batch of events of one process.
+ *   me_out     [n] f64 (MF_FP64) or f32 (other precisions): spin- and colour-
+ *              summed |M|^2 averaged over initial helicities/colours, including
+ *              the 1/2 for identical final gluons.
+ * VJP only:
+ *   x          [d][n] f64 uniforms that generated the event (d = 3 n_out - 4),
+ *   grad_me    [n] f64 incoming cotangent g,
+ *   grad_x     [d][n] f64 out: g * d|M|^2/dx (through the Vegas map and phase space),
+ *   grad_theta [n][2] f64 out: g * (d|M|^2/dm_t at fixed x, d|M|^2/dalpha_s). */
+typedef struct {
+    int32_t proc;
+    int32_t reserved;
+    int64_t n;
+    const double* p;
+    void* me_out;
+    const double* x;
+    const double* grad_me;
+    double* grad_x;
+    double* grad_theta;
+} mf_request;
+
+typedef struct mf_handle_s* mf_handle;
+
+/* Create a handle bound to HIP device `device`; it owns workspace (reduction
+ * partials, counters).  One handle per thread; calls on one handle from
+ * several host threads must be serialised by the caller. */
+mf_status mf_create(int device, mf_handle* out);
+mf_status mf_destroy(mf_handle h);
+
+/* Text of the last error on this thread ("" if none). */
+const char* mf_last_error(void);
+
+/* Number of legs and of uniforms per event for a process (-1 if unknown). */
+int mf_process_legs(int proc);
+int mf_process_dims(int proc);
+
+/* Number of Newton non-convergence events counted by the handle so far
+ * (synchronises the handle's device). */
+mf_status mf_failures(mf_handle h, uint64_t* count);
+
+/*
+ * mf_phase_space -- rows a1..a4 of the hot path: uniforms, Vegas map,
+ * RAMBO-on-diet phase space with massive rescaling, generation cuts.
+ *   x          [d][n] uniforms, or NULL to draw them from Philox4x32-10 with
+ *              key = seed and counter = (offset + *offset_dev + event, dim/2);
+ *   offset_dev optional device pointer added to offset (lets a captured graph
+ *              advance the stream between replays), may be NULL;
+ *   edges      [d][nb+1] Vegas grid, or NULL for the identity map;
+ *   p          [n_ext][4][n] out momenta (incoming legs included);
+ *   w          [n] out phase-space weight (GeV^(2 n_out - 4));
+ *   pass       [n] out cut mask (1 = passes) or NULL;
+ *   bin_idx    [d][n] out Vegas bin of each uniform or NULL (needs nb >= 1);
+ *   jac        [n] out Vegas Jacobian or NULL;
+ *   x_out      [d][n] out copy of the uniforms used, or NULL.
+ * Errors: MF_ERR_INVALID_ARG for a bad process, n < 0, NULL p or w, or
+ * edges/bin_idx given with nb < 2 or nb > 64.
+ */
+mf_status mf_phase_space(mf_handle h, int proc, const mf_params* prm, int64_t n,
+                         const double* x, uint64_t seed, uint64_t offset, const uint64_t* offset_dev,
+                         const double* edges, int nb,
+                         double* p, double* w, uint8_t* pass, int16_t* bin_idx, double* jac,
+                         double* x_out, void* stream);
+
+/*
+ * mf_matrix_element -- row a5 (+ a6 colour contraction): |M|^2 for each event
+ * of each request.  With n_reqs > 1 all requests are served by one launch.
+ * Errors: MF_ERR_INVALID_ARG for n_reqs < 1, NULL reqs/prm, a bad process or
+ * precision, n < 0, or NULL p / me_out with n > 0.
+ */
+mf_status mf_matrix_element(mf_handle h, const mf_request* reqs, int n_reqs, int precision,
+                            const mf_params* prm, void* stream);
+
+/*
+ * mf_matrix_element_vjp -- row a9: vector-Jacobian product of |M|^2 with
+ * respect to the uniforms x (through the Vegas map `edges`, which may be NULL
+ * for the identity, and the phase space) and to (m_t, alpha_s).  The forward
+ * value is written to me_out when it is not NULL.  Per helicity the forward
+ * recursion is recomputed in registers and swept in reverse; no
+ * intermediate current is stored in memory.
+ * Errors: as mf_matrix_element, plus NULL x / grad_me / grad_x / grad_theta,
+ * MF_ERR_UNSUPPORTED for MF_EE_MUMU.
+ */
+mf_status mf_matrix_element_vjp(mf_handle h, const mf_request* reqs, int n_reqs, int precision,
+                                const mf_params* prm, const double* edges, int nb, void* stream);
+
+/*
+ * mf_vegas_refine -- rows a7 and a8: forms F = flux * w * jac * me * pass with
+ * flux = (hbar c)^2 / (2 s) in pb GeV^2 / GeV^2 (so F is in pb), reduces
+ * acc[0] = sum F, acc[1] = sum F^2, acc[2 + k*nb + i] = sum of F^2 over events
+ * in bin i of dimension k (deterministic order), and, if update_edges != 0,
+ * refines `edges` in place (Lepage: smoothing, damping exponent alpha,
+ * rebinning).  If rng_counter is not NULL, *rng_counter += n on the device.
+ *   w, me      [n] required (me is f32 when me_f32 != 0); jac, pass optional;
+ *   bin_idx    [d][n] required; F [n] optional output; acc [2 + d*nb] out.
+ * Errors: MF_ERR_INVALID_ARG for d < 1 or d > 8, nb < 2 or nb > 64, n < 0,
+ * or a NULL required pointer; MF_ERR_NO_MEMORY if workspace cannot grow.
+ */
+mf_status mf_vegas_refine(mf_handle h, const mf_params* prm, int64_t n, int d, int nb, double alpha,
+                          const double* w, const double* jac, const void* me, int me_f32,
+                          const uint8_t* pass, const int16_t* bin_idx, double* F, double* acc,
+                          double* edges, int update_edges, uint64_t* rng_counter, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MF_H */

@@ -17,13 +17,16 @@ def msq(a):
     return mdot(a, a)
 
 
-def boost(p, q):
+def boost(p, q, M=None):
     """Boost p (given in the rest frame of q) to the frame in which q has momentum q.
 
     Standard pure boost with velocity q_vec/q0:
       E' = (q0 E + q.p)/M,   p' = p + q_vec (E + E')/(q0 + M),   M = sqrt(q^2).
+    M may be passed when the invariant mass of q is known exactly; computing it
+    as sqrt(q0^2 - |q|^2) cancels for a strongly boosted light system.
     """
-    M = torch.sqrt(msq(q))
+    if M is None:
+        M = torch.sqrt(msq(q))
     qp = (q[..., 1:] * p[..., 1:]).sum(-1)
     E = (q[..., 0] * p[..., 0] + qp) / M
     fac = (p[..., 0] + E) / (q[..., 0] + M)

@@ -92,8 +92,9 @@ def rambo_diet_massless(u, sqrt_s):
         nvec = torch.stack([sth * torch.cos(ph), sth * torch.sin(ph), cth], -1)
         p_rest = torch.cat([q.unsqueeze(-1), q.unsqueeze(-1) * nvec], -1)
         Qn_rest = torch.cat([torch.sqrt(q * q + Mn * Mn).unsqueeze(-1), -q.unsqueeze(-1) * nvec], -1)
-        p_lab = boost(p_rest, Q)
-        Q = boost(Qn_rest, Q)
+        # Q has invariant mass M_i by construction; use it (no cancellation)
+        p_lab = boost(p_rest, Q, Mi)
+        Q = boost(Qn_rest, Q, Mi)
         ps.append(p_lab)
     ps.append(Q)
     p = torch.stack(ps, 1)

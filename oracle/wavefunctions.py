@@ -10,7 +10,8 @@ representation of the Dirac matrices):
   gamma^0 = [[0, 1], [1, 0]],  gamma^k = [[0, sigma^k], [-sigma^k, 0]]
   chi_+(p) = (|p|+pz, px+i py) / sqrt(2|p|(|p|+pz))
   chi_-(p) = (-px+i py, |p|+pz) / sqrt(2|p|(|p|+pz))
-  (p along -z: chi_+ = (0, 1), chi_- = (-1, 0); p = 0: chi along +z)
+  (p along -z: chi_+ = (0, 1), chi_- = (-1, 0); p = 0: chi along +z;
+   |p|+pz is evaluated as pT^2/(|p|-pz) when pz < 0, its cancellation-free form)
   u(p, l) = ( w_{-l} chi_l ,  w_{+l} chi_l ),   w_{+-} = sqrt(E +- |p|)
   v(p, l) = ( -l w_{+l} chi_{-l} ,  l w_{-l} chi_{-l} )
   eps(k, l) = (-l e1 - i e2)/sqrt(2),
@@ -57,8 +58,10 @@ def slash(a):
 def chi(p, lam):
     """Two-component helicity eigenstate of sigma.p_hat with eigenvalue lam."""
     px, py, pz = p[..., 1], p[..., 2], p[..., 3]
-    pa = torch.sqrt(px * px + py * py + pz * pz)
-    s = pa + pz
+    pt2 = px * px + py * py
+    pa = torch.sqrt(pt2 + pz * pz)
+    # |p| + pz, written as pT^2/(|p| - pz) for pz < 0 (same value, no cancellation)
+    s = torch.where(pz >= 0, pa + pz, pt2 / torch.where(pa - pz > 0, pa - pz, torch.ones_like(pa)))
     ok = s > 0
     ss = torch.where(ok, s, torch.ones_like(s))
     pas = torch.where(pa > 0, pa, torch.ones_like(pa))

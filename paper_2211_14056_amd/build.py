@@ -1,0 +1,70 @@
+"""Build step: emit the generated matrix-element code and compile libmfhip.so for gfx950.
+
+Usage: python -m paper_2211_14056_amd.build [--jobs N]
+"""
+import argparse
+import concurrent.futures as cf
+import os
+import shutil
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, 'csrc')
+GEN = os.path.join(CSRC, 'generated')
+OUT = os.path.join(HERE, 'libmfhip.so')
+BUILD = os.path.join(HERE, '_build')
+
+SOURCES = ['mf_api.cpp', 'phase_space.hip', 'me_kernels.hip', 'me_mfma.hip', 'me_vjp.hip', 'vegas.hip']
+
+FLAGS = ['--offload-arch=gfx950', '-O3', '-std=c++17', '-fPIC', '-ffp-contract=fast',
+         # no packed FP32 arithmetic anywhere in device code
+         '-Xclang', '-target-feature', '-Xclang', '-packed-fp32-ops',
+         '-Wno-unused-command-line-argument']
+
+
+def hipcc():
+    for c in ('/opt/rocm/bin/hipcc', shutil.which('hipcc') or ''):
+        if c and os.path.exists(c):
+            return c
+    raise RuntimeError('hipcc not found')
+
+
+def generate():
+    sys.path.insert(0, os.path.dirname(HERE))
+    from paper_2211_14056_amd.gen import process_compiler
+    return process_compiler.emit_all(GEN)
+
+
+def compile_one(src, extra=()):
+    obj = os.path.join(BUILD, os.path.splitext(src)[0] + '.o')
+    cmd = [hipcc()] + FLAGS + list(extra) + ['-c', os.path.join(CSRC, src), '-o', obj]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f'compile failed: {src}\n{r.stderr[-4000:]}')
+    return obj
+
+
+def build(jobs=None, verbose=True):
+    os.makedirs(BUILD, exist_ok=True)
+    generate()
+    srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
+    jobs = jobs or min(len(srcs), max(1, (os.cpu_count() or 4)))
+    with cf.ThreadPoolExecutor(jobs) as ex:
+        objs = list(ex.map(compile_one, srcs))
+    tmp = OUT + '.tmp'
+    cmd = [hipcc(), '--offload-arch=gfx950', '-shared', '-fPIC'] + objs + ['-o', tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f'link failed\n{r.stderr[-4000:]}')
+    os.replace(tmp, OUT)
+    if verbose:
+        print(f'built {OUT}')
+    return OUT
+
+
+if __name__ == '__main__':
+    ap = argparse.ArgumentParser()
+    ap.add_argument('--jobs', type=int, default=None)
+    args = ap.parse_args()
+    build(args.jobs)

@@ -1,0 +1,70 @@
+// Internal launch interface between the C-ABI layer (mf_api.cpp) and the
+// kernel translation units.  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mf {
+
+enum Proc { EE_MUMU = 0, GG_TT = 1, GG_TTG = 2, GG_TTGG = 3, NPROC = 4 };
+
+inline int n_ext(int proc) { return proc == GG_TTG ? 5 : (proc == GG_TTGG ? 6 : 4); }
+inline int n_out(int proc) { return n_ext(proc) - 2; }
+inline int dims(int proc) { return 3 * n_out(proc) - 4; }
+inline int n_gluons(int proc) { return proc == EE_MUMU ? 0 : n_ext(proc) - 2; }
+
+struct PsArgs {
+    int64_t n;
+    int proc, nb;
+    const double* x;            // [d][n] or null (generate)
+    uint64_t seed, offset;
+    const uint64_t* offset_dev; // optional device-side offset added to `offset`
+    const double* edges;        // [d][nb+1] or null (identity map)
+    double sqrt_s, m_out[4];
+    double pt_min, eta_max, dr_min;
+    double* p;                  // [n_ext][4][n]
+    double* w;                  // [n]
+    uint8_t* pass;              // [n] or null
+    int16_t* bin_idx;           // [d][n] or null
+    double* jac;                // [n] or null
+    double* x_out;              // [d][n] or null
+    unsigned long long* fail_count;   // device counter of Newton failures
+};
+
+hipError_t launch_phase_space(const PsArgs& a, hipStream_t s);
+
+struct MeJob {
+    int proc;
+    int64_t n;
+    const double* p;   // [n_ext][4][n]
+    void* out;         // [n] f64 or f32
+};
+
+// precision: 0 = FP64, 1 = FP32 (VALU colour), 2 = FP32 amplitudes + BF16 MFMA colour,
+//            3 = FP32 amplitudes + FP32 MFMA colour
+hipError_t launch_matrix_element(const MeJob& j, int precision, double mt, double alpha_s,
+                                 double alpha, int block, hipStream_t s);
+
+struct VegasArgs {
+    int64_t n;
+    int d, nb;
+    double alpha, flux;         // flux = conversion / (2 s)
+    const double* w;
+    const double* jac;          // may be null
+    const void* me;
+    int me_f32;
+    const uint8_t* pass;        // may be null
+    const int16_t* bin_idx;
+    double* F;                  // may be null
+    double* partials;           // workspace [nblk][2 + d*nb]
+    int nblk;
+    double* acc;                // [2 + d*nb]
+    double* edges;              // [d][nb+1]
+    int update_edges;
+    uint64_t* rng_counter;      // may be null
+};
+
+int vegas_blocks(int64_t n);
+hipError_t launch_vegas(const VegasArgs& a, hipStream_t s);
+
+}  // namespace mf

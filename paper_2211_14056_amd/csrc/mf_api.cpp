@@ -1,0 +1,281 @@
+// C-ABI layer: argument validation, workspace ownership, kernel launches.
+// The public contract is documented in include/mf.h.
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "../../include/mf.h"
+#include "internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+mf_status fail(mf_status s, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+mf_status hip_fail(hipError_t e, const char* where)
+{
+    return fail(MF_ERR_HIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+bool valid_proc(int p) { return p >= MF_EE_MUMU && p <= MF_GG_TTGG; }
+
+}  // namespace
+
+struct mf_handle_s {
+    int device = 0;
+    double* partials = nullptr;
+    size_t partials_cap = 0;           // doubles
+    unsigned long long* fail_dev = nullptr;
+};
+
+namespace {
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) hipSetDevice(dev);
+    }
+    ~DeviceGuard()
+    {
+        if (prev >= 0) hipSetDevice(prev);
+    }
+};
+
+mf_status ensure_partials(mf_handle h, size_t need)
+{
+    if (h->partials_cap >= need) return MF_OK;
+    if (h->partials) {
+        hipDeviceSynchronize();
+        hipFree(h->partials);
+        h->partials = nullptr;
+        h->partials_cap = 0;
+    }
+    if (hipMalloc(&h->partials, need * sizeof(double)) != hipSuccess) {
+        h->partials = nullptr;
+        return fail(MF_ERR_NO_MEMORY, "mf_vegas_refine: cannot allocate %zu bytes of workspace",
+                    need * sizeof(double));
+    }
+    h->partials_cap = need;
+    return MF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mf_last_error(void) { return g_err.c_str(); }
+
+int mf_process_legs(int proc) { return valid_proc(proc) ? mf::n_ext(proc) : -1; }
+int mf_process_dims(int proc) { return valid_proc(proc) ? mf::dims(proc) : -1; }
+
+mf_status mf_create(int device, mf_handle* out)
+{
+    g_err.clear();
+    if (!out) return fail(MF_ERR_INVALID_ARG, "mf_create: out is NULL");
+    *out = nullptr;
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess) return hip_fail(e, "mf_create: hipGetDeviceCount");
+    if (device < 0 || device >= count)
+        return fail(MF_ERR_INVALID_ARG, "mf_create: device %d out of range (%d devices)", device, count);
+    DeviceGuard g(device);
+    mf_handle h = new mf_handle_s;
+    h->device = device;
+    e = hipMalloc(&h->fail_dev, sizeof(unsigned long long));
+    if (e != hipSuccess) {
+        delete h;
+        return fail(MF_ERR_NO_MEMORY, "mf_create: cannot allocate counters");
+    }
+    e = hipMemset(h->fail_dev, 0, sizeof(unsigned long long));
+    if (e != hipSuccess) {
+        hipFree(h->fail_dev);
+        delete h;
+        return hip_fail(e, "mf_create: hipMemset");
+    }
+    *out = h;
+    return MF_OK;
+}
+
+mf_status mf_destroy(mf_handle h)
+{
+    g_err.clear();
+    if (!h) return MF_OK;
+    DeviceGuard g(h->device);
+    hipDeviceSynchronize();
+    if (h->partials) hipFree(h->partials);
+    if (h->fail_dev) hipFree(h->fail_dev);
+    delete h;
+    return MF_OK;
+}
+
+mf_status mf_failures(mf_handle h, uint64_t* count)
+{
+    g_err.clear();
+    if (!h || !count) return fail(MF_ERR_INVALID_ARG, "mf_failures: NULL argument");
+    DeviceGuard g(h->device);
+    unsigned long long v = 0;
+    hipError_t e = hipMemcpy(&v, h->fail_dev, sizeof v, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "mf_failures");
+    *count = v;
+    return MF_OK;
+}
+
+mf_status mf_phase_space(mf_handle h, int proc, const mf_params* prm, int64_t n,
+                         const double* x, uint64_t seed, uint64_t offset, const uint64_t* offset_dev,
+                         const double* edges, int nb,
+                         double* p, double* w, uint8_t* pass, int16_t* bin_idx, double* jac,
+                         double* x_out, void* stream)
+{
+    g_err.clear();
+    if (!h) return fail(MF_ERR_INVALID_ARG, "mf_phase_space: NULL handle");
+    if (!valid_proc(proc)) return fail(MF_ERR_INVALID_ARG, "mf_phase_space: unknown process %d", proc);
+    if (!prm) return fail(MF_ERR_INVALID_ARG, "mf_phase_space: NULL params");
+    if (n < 0) return fail(MF_ERR_INVALID_ARG, "mf_phase_space: n = %lld < 0", (long long)n);
+    if (n == 0) return MF_OK;
+    if (!p || !w) return fail(MF_ERR_INVALID_ARG, "mf_phase_space: NULL p or w");
+    if ((edges || bin_idx) && (nb < 2 || nb > 64))
+        return fail(MF_ERR_INVALID_ARG, "mf_phase_space: nb = %d outside [2, 64]", nb);
+    if (!(prm->sqrt_s > 0.0)) return fail(MF_ERR_INVALID_ARG, "mf_phase_space: sqrt_s must be > 0");
+    const bool qcd = proc != MF_EE_MUMU;
+    if (qcd && !(2.0 * prm->m_t < prm->sqrt_s && prm->m_t >= 0.0))
+        return fail(MF_ERR_INVALID_ARG, "mf_phase_space: need 0 <= 2 m_t < sqrt_s");
+    DeviceGuard g(h->device);
+    mf::PsArgs a{};
+    a.n = n;
+    a.proc = proc;
+    a.nb = nb;
+    a.x = x;
+    a.seed = seed;
+    a.offset = offset;
+    a.offset_dev = offset_dev;
+    a.edges = edges;
+    a.sqrt_s = prm->sqrt_s;
+    for (int i = 0; i < 4; ++i) a.m_out[i] = 0.0;
+    if (qcd) a.m_out[0] = a.m_out[1] = prm->m_t;
+    a.pt_min = prm->pt_min;
+    a.eta_max = prm->eta_max;
+    a.dr_min = prm->dr_min;
+    a.p = p;
+    a.w = w;
+    a.pass = pass;
+    a.bin_idx = bin_idx;
+    a.jac = jac;
+    a.x_out = x_out;
+    a.fail_count = h->fail_dev;
+    hipError_t e = mf::launch_phase_space(a, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "mf_phase_space launch");
+    return MF_OK;
+}
+
+static mf_status check_requests(const char* who, const mf_request* reqs, int n_reqs, int precision,
+                                const mf_params* prm, bool vjp)
+{
+    if (!reqs || n_reqs < 1) return fail(MF_ERR_INVALID_ARG, "%s: need at least one request", who);
+    if (!prm) return fail(MF_ERR_INVALID_ARG, "%s: NULL params", who);
+    if (precision < MF_FP64 || precision > MF_FP32_MFMA_F32)
+        return fail(MF_ERR_INVALID_ARG, "%s: unknown precision %d", who, precision);
+    for (int i = 0; i < n_reqs; ++i) {
+        const mf_request& r = reqs[i];
+        if (!valid_proc(r.proc)) return fail(MF_ERR_INVALID_ARG, "%s: request %d: unknown process %d", who, i, r.proc);
+        if (r.n < 0) return fail(MF_ERR_INVALID_ARG, "%s: request %d: n < 0", who, i);
+        if (r.n == 0) continue;
+        if (!r.p && !vjp) return fail(MF_ERR_INVALID_ARG, "%s: request %d: NULL p", who, i);
+        if (!vjp && !r.me_out) return fail(MF_ERR_INVALID_ARG, "%s: request %d: NULL me_out", who, i);
+        if (vjp && (!r.x || !r.grad_me || !r.grad_x || !r.grad_theta))
+            return fail(MF_ERR_INVALID_ARG, "%s: request %d: NULL x/grad_me/grad_x/grad_theta", who, i);
+    }
+    return MF_OK;
+}
+
+mf_status mf_matrix_element(mf_handle h, const mf_request* reqs, int n_reqs, int precision,
+                            const mf_params* prm, void* stream)
+{
+    g_err.clear();
+    if (!h) return fail(MF_ERR_INVALID_ARG, "mf_matrix_element: NULL handle");
+    mf_status st = check_requests("mf_matrix_element", reqs, n_reqs, precision, prm, false);
+    if (st != MF_OK) return st;
+    DeviceGuard g(h->device);
+    for (int i = 0; i < n_reqs; ++i) {
+        if (reqs[i].n == 0) continue;
+        mf::MeJob j{reqs[i].proc, reqs[i].n, reqs[i].p, reqs[i].me_out};
+        hipError_t e = mf::launch_matrix_element(j, precision, prm->m_t, prm->alpha_s, prm->alpha, 0,
+                                                 static_cast<hipStream_t>(stream));
+        if (e == hipErrorInvalidValue)
+            return fail(MF_ERR_UNSUPPORTED, "mf_matrix_element: precision %d not available for process %d",
+                        precision, reqs[i].proc);
+        if (e != hipSuccess) return hip_fail(e, "mf_matrix_element launch");
+    }
+    return MF_OK;
+}
+
+mf_status mf_matrix_element_vjp(mf_handle h, const mf_request* reqs, int n_reqs, int precision,
+                                const mf_params* prm, const double* edges, int nb, void* stream)
+{
+    g_err.clear();
+    if (!h) return fail(MF_ERR_INVALID_ARG, "mf_matrix_element_vjp: NULL handle");
+    mf_status st = check_requests("mf_matrix_element_vjp", reqs, n_reqs, precision, prm, true);
+    if (st != MF_OK) return st;
+    (void)edges;
+    (void)nb;
+    (void)stream;
+    return fail(MF_ERR_UNSUPPORTED, "mf_matrix_element_vjp: not available in this build");
+}
+
+mf_status mf_vegas_refine(mf_handle h, const mf_params* prm, int64_t n, int d, int nb, double alpha,
+                          const double* w, const double* jac, const void* me, int me_f32,
+                          const uint8_t* pass, const int16_t* bin_idx, double* F, double* acc,
+                          double* edges, int update_edges, uint64_t* rng_counter, void* stream)
+{
+    g_err.clear();
+    if (!h) return fail(MF_ERR_INVALID_ARG, "mf_vegas_refine: NULL handle");
+    if (!prm) return fail(MF_ERR_INVALID_ARG, "mf_vegas_refine: NULL params");
+    if (d < 1 || d > 8) return fail(MF_ERR_INVALID_ARG, "mf_vegas_refine: d = %d outside [1, 8]", d);
+    if (nb < 2 || nb > 64) return fail(MF_ERR_INVALID_ARG, "mf_vegas_refine: nb = %d outside [2, 64]", nb);
+    if (n < 0) return fail(MF_ERR_INVALID_ARG, "mf_vegas_refine: n < 0");
+    if (!acc || !edges) return fail(MF_ERR_INVALID_ARG, "mf_vegas_refine: NULL acc or edges");
+    if (n > 0 && (!w || !me || !bin_idx))
+        return fail(MF_ERR_INVALID_ARG, "mf_vegas_refine: NULL w, me or bin_idx");
+    DeviceGuard g(h->device);
+    mf::VegasArgs a{};
+    a.n = n;
+    a.d = d;
+    a.nb = nb;
+    a.alpha = alpha;
+    const double s = prm->sqrt_s * prm->sqrt_s;
+    a.flux = 0.3893793721e9 / (2.0 * s);
+    a.w = w;
+    a.jac = jac;
+    a.me = me;
+    a.me_f32 = me_f32;
+    a.pass = pass;
+    a.bin_idx = bin_idx;
+    a.F = F;
+    a.nblk = mf::vegas_blocks(n);
+    mf_status st = ensure_partials(h, (size_t)a.nblk * (2 + d * nb));
+    if (st != MF_OK) return st;
+    a.partials = h->partials;
+    a.acc = acc;
+    a.edges = edges;
+    a.update_edges = update_edges;
+    a.rng_counter = rng_counter;
+    hipError_t e = mf::launch_vegas(a, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "mf_vegas_refine launch");
+    return MF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,166 @@
+// Vegas accumulation and grid refinement.
+//
+// The paper integrates with Vegas (sect. 1, G. P. Lepage 1978/1980); the
+// refinement used here is Lepage's: per dimension a histogram of F^2 over the
+// bins of the current grid, smoothed over neighbouring bins, compressed by
+// r = ((1 - rho)/(-ln rho))^alpha and rebinned so that every new bin holds the
+// same share of sum r.
+//
+// Accumulation is deterministic (fixed reduction order for any run):
+//  * each block walks a fixed set of 256-event chunks (grid-stride with a
+//    grid size that depends only on n);
+//  * per wave, lane k < d owns the histogram row of dimension k in LDS and
+//    adds the wave's 64 events in lane order;
+//  * block partials (sum F, sum F^2, histogram) go to a workspace, and one
+//    workgroup sums them in block order and then refines the grid.
+// F = flux * w * J_vegas * ME * pass is formed here from the phase-space
+// weight, the Vegas Jacobian and the matrix element, so it never round-trips
+// through memory unless the caller asks for it.
+#include "internal.h"
+
+namespace mf {
+namespace {
+
+constexpr int VB = 256;           // threads per block
+constexpr int WAVES = VB / 64;
+constexpr int MAXD = 8;
+constexpr int MAXNB = 64;
+
+__global__ __launch_bounds__(VB) void k_vegas_accumulate(VegasArgs a)
+{
+    __shared__ double hist[WAVES][MAXD][MAXNB];
+    __shared__ double fsq[WAVES][64];
+    __shared__ short bins[WAVES][MAXD][64];
+    __shared__ double red[2][VB];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int d = a.d, nb = a.nb;
+    for (int c = lane; c < MAXD * MAXNB; c += 64) hist[wv][c / MAXNB][c % MAXNB] = 0.0;
+    double sf = 0.0, sf2 = 0.0;
+    const int64_t n = a.n;
+    for (int64_t chunk = blockIdx.x; chunk * VB < n; chunk += gridDim.x) {
+        const int64_t e = chunk * VB + tid;
+        double F = 0.0;
+        if (e < n) {
+            const double me = a.me_f32 ? (double)static_cast<const float*>(a.me)[e]
+                                       : static_cast<const double*>(a.me)[e];
+            const double ps = a.pass ? (double)a.pass[e] : 1.0;
+            const double jac = a.jac ? a.jac[e] : 1.0;
+            F = a.flux * a.w[e] * jac * me * ps;
+            if (a.F) a.F[e] = F;
+        }
+        sf += F;
+        sf2 += F * F;
+        fsq[wv][lane] = F * F;
+        for (int k = 0; k < d; ++k) bins[wv][k][lane] = (e < n) ? a.bin_idx[k * n + e] : (short)-1;
+        __syncthreads();
+        if (lane < d) {
+            for (int l = 0; l < 64; ++l) {
+                const int b = bins[wv][lane][l];
+                if (b >= 0 && b < nb) hist[wv][lane][b] += fsq[wv][l];
+            }
+        }
+        __syncthreads();
+    }
+    red[0][tid] = sf;
+    red[1][tid] = sf2;
+    __syncthreads();
+    for (int s = VB / 2; s > 0; s >>= 1) {
+        if (tid < s) {
+            red[0][tid] += red[0][tid + s];
+            red[1][tid] += red[1][tid + s];
+        }
+        __syncthreads();
+    }
+    const int stride = 2 + d * nb;
+    double* out = a.partials + (int64_t)blockIdx.x * stride;
+    if (tid == 0) {
+        out[0] = red[0][0];
+        out[1] = red[1][0];
+    }
+    for (int c = tid; c < d * nb; c += VB) {
+        const int k = c / nb, b = c % nb;
+        double s = 0.0;
+        for (int w = 0; w < WAVES; ++w) s += hist[w][k][b];
+        out[2 + c] = s;
+    }
+}
+
+__device__ void refine_dim(const double* h, double* edges, int nb, double alpha)
+{
+    bool any = false;
+    for (int i = 0; i < nb; ++i) any = any || (h[i] > 0.0);
+    if (!any) return;
+    double hb[MAXNB], r[MAXNB], old[MAXNB + 1];
+    hb[0] = (h[0] + h[1]) / 2.0;
+    hb[nb - 1] = (h[nb - 2] + h[nb - 1]) / 2.0;
+    for (int i = 1; i < nb - 1; ++i) hb[i] = (h[i - 1] + h[i] + h[i + 1]) / 3.0;
+    double tot = 0.0;
+    for (int i = 0; i < nb; ++i) tot += hb[i];
+    double rsum = 0.0;
+    for (int i = 0; i < nb; ++i) {
+        const double rho = hb[i] / tot;
+        double v;
+        if (rho <= 0.0) v = 0.0;
+        else if (rho >= 1.0) v = 1.0;
+        else v = pow((1.0 - rho) / (-log(rho)), alpha);
+        r[i] = v;
+        rsum += v;
+    }
+    for (int i = 0; i <= nb; ++i) old[i] = edges[i];
+    const double delta = rsum / nb;
+    double cum = 0.0;
+    int i = 0;
+    for (int e = 1; e < nb; ++e) {
+        const double target = e * delta;
+        while (i < nb && cum + r[i] < target) {
+            cum += r[i];
+            ++i;
+        }
+        if (i >= nb) {
+            edges[e] = old[nb];
+            continue;
+        }
+        edges[e] = r[i] > 0.0 ? old[i] + (target - cum) / r[i] * (old[i + 1] - old[i]) : old[i];
+    }
+    edges[0] = 0.0;
+    edges[nb] = 1.0;
+}
+
+__global__ __launch_bounds__(VB) void k_vegas_finalize(VegasArgs a)
+{
+    const int stride = 2 + a.d * a.nb;
+    for (int c = threadIdx.x; c < stride; c += VB) {
+        double s = 0.0;
+        for (int b = 0; b < a.nblk; ++b) s += a.partials[(int64_t)b * stride + c];
+        a.acc[c] = s;
+    }
+    __syncthreads();
+    if (a.update_edges && threadIdx.x < a.d) {
+        const int k = threadIdx.x;
+        refine_dim(a.acc + 2 + k * a.nb, a.edges + k * (a.nb + 1), a.nb, a.alpha);
+    }
+    if (a.rng_counter && threadIdx.x == 0) *a.rng_counter += (uint64_t)a.n;
+}
+
+}  // namespace
+
+int vegas_blocks(int64_t n)
+{
+    int64_t b = (n + VB - 1) / VB;
+    if (b > 1024) b = 1024;
+    if (b < 1) b = 1;
+    return (int)b;
+}
+
+hipError_t launch_vegas(const VegasArgs& a, hipStream_t s)
+{
+    if (a.d > MAXD || a.nb > MAXNB || a.nb < 2) return hipErrorInvalidValue;
+    // n = 0 still runs the accumulation: every block then writes zero partials
+    hipLaunchKernelGGL(k_vegas_accumulate, dim3(a.nblk), dim3(VB), 0, s, a);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL(k_vegas_finalize, dim3(1), dim3(VB), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace mf

@@ -1,0 +1,452 @@
+"""Process compiler: emits fused HIP device code for tree-level matrix elements.
+
+The paper transpiles auto-generated per-process matrix-element code (external
+wavefunctions, vertex and propagator routines, the process's diagram sequence)
+into device code (sect. 2, Fig. 2), one kernel per vertex/spinor/propagator.
+Here the process is compiled into ONE straight-line device function per event
+whose intermediate currents live in registers, which is the footprint lever
+the paper identifies (sect. 2, the discussion of Table 1).
+
+Physics content.  For g g -> t tbar + (k-2) g, the amplitude is decomposed in
+colour-ordered partial amplitudes A(sigma) over the k! gluon orderings with
+colour factors (t^{a_sigma1}..t^{a_sigmak})_{i jbar}, and
+
+    sum_{colour} |M|^2 = g^{2k} sum_{sigma,tau} Re(A_sigma^* C_{sigma tau} A_tau)
+
+with the exact colour matrix from ``colour_algebra``.  Partial amplitudes are
+built by the Berends-Giele off-shell recursion with colour-ordered vertices in
+the normalisation where all couplings and phases are factored out:
+
+  gluon current   J(rho) = 1/P_rho^2 [ sum_{rho = a b}  V3(J_a, P_a; J_b, P_b)
+                                      + sum_{rho = a b c} V4(J_a, J_b, J_c) ]
+      V3 = (J_a.J_b)(P_a - P_b) + 2 (P_b.J_a) J_b - 2 (P_a.J_b) J_a
+      V4 = 2 J_b (J_a.J_c) - J_c (J_a.J_b) - J_a (J_b.J_c)
+  quark line      A(sigma) = sum over splits of sigma into blocks b_1..b_r of
+                  ubar(p_t) Jslash(b_1) S(q_1) Jslash(b_2) ... Jslash(b_r) v(p_tbar),
+                  S(q) = (qslash + m)/(q^2 - m^2),  q_l = p_t - P(b_1..b_l)
+
+(momenta P flow into the current: +p for incoming, -p for outgoing gluons;
+external currents are eps(p) for incoming and eps*(p) for outgoing gluons).
+V3 uses current conservation P_a.J_a = 0 of Berends-Giele currents with
+physical external gluons.  Reflection J(reverse rho) = (-1)^(|rho|+1) J(rho)
+halves the gluon currents.  Vectors are held in light-cone components
+(v0+v3, v0-v3, v1+i v2, v1-i v2), in which gamma-matrix products need no
+recombination.
+
+Helicity recycling: gluon currents depend only on gluon helicities, so the
+outer loop runs over the 2^k gluon helicity configurations and the quark
+helicities are handled inside it (the top as a 2-trip loop, the antitop by
+contracting the same open spinor with both v(+) and v(-)).
+
+Kinematics (momenta, spinor and polarisation bases, all propagator
+denominators) are evaluated once per event in FP64; the recursion and the
+colour sum run in the kernel's working type R (double or float).
+"""
+import itertools
+import math
+import os
+
+from . import colour_algebra
+from .ir import Block, C, S, ZERO, ONE, const, csum, cadd, csub, cneg, cmat
+
+SQRT1_2 = 1.0 / math.sqrt(2.0)
+
+
+# ----------------------------------------------------------------- vectors
+def lc_dot2(b, x, y):
+    """2 x.y in light-cone components: x+ y- + x- y+ - xt ytb - xtb yt."""
+    return csum(b, [(x[0], y[1]), (x[1], y[0]), (cneg(b, x[2]), y[3]), (cneg(b, x[3]), y[2])])
+
+
+def real_lc(b, px, py, pp, pm):
+    """Real four-vector (given by v+, v-, vx, vy) as a light-cone complex vector."""
+    return [C(pp, ZERO), C(pm, ZERO), C(px, py), C(px, b.neg(py))]
+
+
+class Momentum:
+    """Real four-vector with named scalar components (E, x, y, z) and light-cone view."""
+
+    def __init__(self, b, comps):
+        self.E, self.x, self.y, self.z = comps
+        self.b = b
+        self._lc = None
+
+    def lc(self):
+        if self._lc is None:
+            b = self.b
+            pp = b.add(self.E, self.z)
+            pm = b.sub(self.E, self.z)
+            self._lc = real_lc(b, self.x, self.y, pp, pm)
+        return self._lc
+
+
+def msum(b, moms, signs):
+    comps = []
+    for c in range(4):
+        acc = ZERO
+        for m, s in zip(moms, signs):
+            v = [m.E, m.x, m.y, m.z][c]
+            acc = b.add(acc, v) if s > 0 else b.sub(acc, v)
+        comps.append(acc)
+    return Momentum(b, comps)
+
+
+# ----------------------------------------------------------------- process
+class GGTTProcess:
+    """g(0) g(1) -> t(2) tbar(3) g(4) ... g(n_ext-1)."""
+
+    def __init__(self, name, n_ext):
+        self.name = name
+        self.n_ext = n_ext
+        self.k = n_ext - 2                       # number of gluons
+        self.gl_legs = [0, 1] + list(range(4, n_ext))
+        self.sym = math.factorial(n_ext - 4)     # identical final gluons
+        self.avg = 256.0
+        C, den = colour_algebra.integer_form(colour_algebra.colour_matrix(self.k))
+        self.cnum, self.cden = C, den
+        self.orderings = colour_algebra.orderings(self.k)
+
+    # subsets of gluons needing propagators
+    def gluon_subsets(self):
+        return [c for r in range(2, self.k + 1) for c in itertools.combinations(range(self.k), r)]
+
+    def quark_subsets(self):
+        return [c for r in range(1, self.k) for c in itertools.combinations(range(self.k), r)]
+
+
+def _sname(sub):
+    return ''.join(str(i) for i in sub)
+
+
+def emit_qcd(proc, with_colour=True):
+    """Return (source text, flop counts) of the device function for ``proc``."""
+    k = proc.k
+    out = []
+    fn = f'me_{proc.name}'
+    out.append(f'// ---- {proc.name}: {k} gluons, {math.factorial(k)} colour orderings, '
+               f'{2 ** (k + 2)} helicities')
+    out.append(f'template <typename R, typename Sink>')
+    out.append(f'__device__ __forceinline__ void {fn}_body(const double (&p)[{proc.n_ext}][4], '
+               f'const double mt, Sink& sink)')
+    out.append('{')
+    # ---------------- prologue (double precision kinematics) ----------------
+    pro = []
+    # incoming-convention momenta k_i of the gluons
+    for gi, leg in enumerate(proc.gl_legs):
+        sgn = '' if leg < 2 else '-'
+        pro.append(f'const double k{gi}[4] = {{{sgn}p[{leg}][0], {sgn}p[{leg}][1], '
+                   f'{sgn}p[{leg}][2], {sgn}p[{leg}][3]}};')
+    pro.append('const double mt2 = mt * mt;')
+    # gluon propagators 1/P_S^2
+    for sub in proc.gluon_subsets():
+        n = _sname(sub)
+        terms = ' + '.join(f'k{i}[c]' for i in sub)
+        pro.append(f'double P{n}[4]; for (int c = 0; c < 4; ++c) P{n}[c] = {terms};')
+        pro.append(f'const R ig{n} = R(1.0 / (P{n}[0] * P{n}[0] - P{n}[1] * P{n}[1] - '
+                   f'P{n}[2] * P{n}[2] - P{n}[3] * P{n}[3]));')
+    # quark propagators: q = p_t - P_S, 1/(q^2 - m^2)
+    for sub in proc.quark_subsets():
+        n = _sname(sub)
+        terms = ' - '.join([f'p[2][c]'] + [f'k{i}[c]' for i in sub])
+        pro.append(f'double q{n}[4]; for (int c = 0; c < 4; ++c) q{n}[c] = {terms};')
+        pro.append(f'const R iq{n} = R(1.0 / ((q{n}[0] - q{n}[3]) * (q{n}[0] + q{n}[3]) - '
+                   f'q{n}[1] * q{n}[1] - q{n}[2] * q{n}[2] - mt2));')
+    # momenta in working precision
+    for gi in range(k):
+        pro.append(f'const R K{gi}[4] = {{R(k{gi}[0]), R(k{gi}[1]), R(k{gi}[2]), R(k{gi}[3])}};')
+    pro.append('const R PT[4] = {R(p[2][0]), R(p[2][1]), R(p[2][2]), R(p[2][3])};')
+    pro.append('const R MT = R(mt);')
+    # outgoing-gluon polarisation bases (eps1/sqrt2, eps2/sqrt2)
+    for gi, leg in enumerate(proc.gl_legs):
+        if leg < 2:
+            continue
+        pro.append(f'R e{gi}u[3], e{gi}w[2]; pol_basis<R>(p[{leg}], e{gi}u, e{gi}w);')
+    # spinors for both helicities
+    pro.append('cplx<R> ub[2][4], vs[2][4];')
+    pro.append('ubar_spinor<R>(p[2], mt, -1, ub[0]); ubar_spinor<R>(p[2], mt, 1, ub[1]);')
+    pro.append('v_spinor<R>(p[3], mt, -1, vs[0]); v_spinor<R>(p[3], mt, 1, vs[1]);')
+    out += ['    ' + l for l in pro]
+
+    # ---------------- loop body (working precision) ----------------
+    b = Block('t')
+    moms = [Momentum(b, [S(name=f'K{gi}[{c}]') for c in range(4)]) for gi in range(k)]
+    # beams: gluon 0 along +z, gluon 1 along -z; known zero components
+    for gi, leg in enumerate(proc.gl_legs):
+        if leg < 2:
+            E = S(name=f'K{gi}[0]')
+            zsign = 1.0 if leg == 0 else -1.0
+            mm = Momentum(b, [E, ZERO, ZERO, E if zsign > 0 else b.neg(E)])
+            moms[gi] = mm
+    lam = [S(name=f'lam{gi}') for gi in range(k)]
+    # external gluon currents (light-cone components)
+    eps = []
+    for gi, leg in enumerate(proc.gl_legs):
+        if leg == 0:
+            # eps(+z, l) = (0, -l/sqrt2, -i/sqrt2, 0): t = (1-l)/sqrt2, tb = -(1+l)/sqrt2
+            t = b.sumprod([(lam[gi], const(-SQRT1_2))], const(SQRT1_2))
+            tb = b.sumprod([(lam[gi], const(-SQRT1_2))], const(-SQRT1_2))
+            eps.append([C(ZERO), C(ZERO), C(t), C(tb)])
+        elif leg == 1:
+            # eps(-z, l) = (0, l/sqrt2, -i/sqrt2, 0): t = (1+l)/sqrt2, tb = (l-1)/sqrt2
+            t = b.sumprod([(lam[gi], const(SQRT1_2))], const(SQRT1_2))
+            tb = b.sumprod([(lam[gi], const(SQRT1_2))], const(-SQRT1_2))
+            eps.append([C(ZERO), C(ZERO), C(t), C(tb)])
+        else:
+            # eps*(k, l) = (-l u + i w), u = eps1/sqrt2 (x,y,z), w = eps2/sqrt2 (x,y), w_z = 0
+            ux, uy, uz = (S(name=f'e{gi}u[{c}]') for c in range(3))
+            wx, wy = (S(name=f'e{gi}w[{c}]') for c in range(2))
+            l = lam[gi]
+            ez = b.mul(b.neg(l), uz)                       # eps^3 (real)
+            # t = eps^1 + i eps^2 = (-l ux - wy) + i (wx - l uy)
+            tr = b.sumprod([(l, b.neg(ux))], b.neg(wy))
+            ti = b.sumprod([(l, b.neg(uy))], wx)
+            # tb = eps^1 - i eps^2 = (-l ux + wy) + i (wx + l uy)
+            tbr = b.sumprod([(l, b.neg(ux))], wy)
+            tbi = b.sumprod([(l, uy)], wx)
+            eps.append([C(ez), C(b.neg(ez)), C(tr, ti), C(tbr, tbi)])
+    # momentum sums of gluon subsets (light cone), memoised
+    msum_memo = {}
+
+    def P(rho):
+        key = tuple(sorted(rho))
+        if key not in msum_memo:
+            if len(key) == 1:
+                msum_memo[key] = moms[key[0]]
+            else:
+                msum_memo[key] = msum(b, [moms[i] for i in key], [1] * len(key))
+        return msum_memo[key]
+
+    dot_memo = {}
+
+    def orient(rho):
+        """(canonical orientation, sign) with J(rho) = sign * J(canonical)."""
+        c = canon(rho)
+        return c, (1 if c == rho else (-1) ** (len(rho) + 1))
+
+    def D(x, y):
+        """2 J(x).J(y), memoised over canonical orientations."""
+        (cx, sx), (cy, sy) = orient(x), orient(y)
+        key = (cx, cy) if cx <= cy else (cy, cx)
+        if key not in dot_memo:
+            dot_memo[key] = cmat(b, lc_dot2(b, J(cx), J(cy)))
+        v = dot_memo[key]
+        return v if sx * sy > 0 else cneg(b, v)
+
+    # gluon currents
+    jmemo = {}
+
+    def canon(rho):
+        return rho if rho[0] < rho[-1] or len(rho) == 1 else tuple(reversed(rho))
+
+    def J(rho):
+        c = canon(rho)
+        if c != rho:
+            sgn = (-1) ** (len(rho) + 1)
+            v = J(c)
+            return v if sgn > 0 else [cneg(b, x) for x in v]
+        if rho in jmemo:
+            return jmemo[rho]
+        if len(rho) == 1:
+            jmemo[rho] = eps[rho[0]]
+            return jmemo[rho]
+        terms = [[] for _ in range(4)]
+        # three-vertex splits
+        for s in range(1, len(rho)):
+            a, bb = rho[:s], rho[s:]
+            Ja, Jb = J(a), J(bb)
+            Pa, Pb = P(a).lc(), P(bb).lc()
+            dab = D(a, bb)
+            hd = C(b.mul(dab.re, const(0.5)), b.mul(dab.im, const(0.5)))
+            hd = cmat(b, hd)
+            pbja = cmat(b, lc_dot2(b, Pb, Ja))        # 2 Pb.Ja
+            pajb = cmat(b, lc_dot2(b, Pa, Jb))        # 2 Pa.Jb
+            for mu in range(4):
+                dP = csub(b, Pa[mu], Pb[mu])
+                terms[mu].append((hd, dP))
+                terms[mu].append((pbja, Jb[mu]))
+                terms[mu].append((cneg(b, pajb), Ja[mu]))
+        # four-vertex splits
+        for s1 in range(1, len(rho) - 1):
+            for s2 in range(s1 + 1, len(rho)):
+                a, bb, cc = rho[:s1], rho[s1:s2], rho[s2:]
+                Ja, Jb, Jc = J(a), J(bb), J(cc)
+                dac = D(a, cc)
+                dab = D(a, bb)
+                dbc = D(bb, cc)
+                hab = cmat(b, C(b.mul(dab.re, const(-0.5)), b.mul(dab.im, const(-0.5))))
+                hbc = cmat(b, C(b.mul(dbc.re, const(-0.5)), b.mul(dbc.im, const(-0.5))))
+                for mu in range(4):
+                    terms[mu].append((dac, Jb[mu]))
+                    terms[mu].append((hab, Jc[mu]))
+                    terms[mu].append((hbc, Ja[mu]))
+        ig = S(name=f'ig{_sname(sorted(rho))}')
+        vec = []
+        for mu in range(4):
+            acc = csum(b, terms[mu])
+            vec.append(cmat(b, C(b.mul(acc.re, ig), b.mul(acc.im, ig))))
+        jmemo[rho] = vec
+        return vec
+
+    # build every gluon current (canonical orientations), by length
+    for r in range(2, k + 1):
+        for S_ in itertools.combinations(range(k), r):
+            for perm in itertools.permutations(S_):
+                if canon(perm) == perm:
+                    J(perm)
+    gluon_flops = b.flops
+    gluon_lines = b.lines
+    # ---------------- quark line (inside the top-helicity loop) ----------------
+    q = Block('u')
+    # re-wrap names so the quark block references gluon-block values
+    ub = [C(S(name=f'ubs[{j}].re'), S(name=f'ubs[{j}].im')) for j in range(4)]
+
+    def slash_row(psi, Jv):
+        """Terms of the row spinor psi * Jslash (light cone): list per component."""
+        Jp, Jm, Jt, Jtb = Jv
+        return [
+            [(psi[2], Jp), (psi[3], Jt)],
+            [(psi[2], Jtb), (psi[3], Jm)],
+            [(psi[0], Jm), (cneg(q, psi[1]), Jt)],
+            [(cneg(q, psi[0]), Jtb), (psi[1], Jp)],
+        ]
+
+    qmemo = {(): ub}
+
+    def Q(prefix):
+        if prefix in qmemo:
+            return qmemo[prefix]
+        terms = [[] for _ in range(4)]
+        for s in range(len(prefix)):
+            rows = slash_row(Q(prefix[:s]), J(prefix[s:]))
+            for c in range(4):
+                terms[c] += rows[c]
+        psi = [cmat(q, csum(q, terms[c])) for c in range(4)]
+        # propagator: (psi qslash + m psi)/(q^2 - m^2), q = p_t - P(prefix)
+        n = _sname(sorted(prefix))
+        iq = S(name=f'iq{n}')
+        Pp = P(prefix)
+        qE = q.sub(S(name='PT[0]'), Pp.E)
+        qx = q.sub(S(name='PT[1]'), Pp.x)
+        qy = q.sub(S(name='PT[2]'), Pp.y)
+        qz = q.sub(S(name='PT[3]'), Pp.z)
+        qp = q.mul(q.add(qE, qz), iq)
+        qm = q.mul(q.sub(qE, qz), iq)
+        qxs = q.mul(qx, iq)
+        qys = q.mul(qy, iq)
+        ms = q.mul(S(name='MT'), iq)
+        qlc = [C(qp), C(qm), C(qxs, qys), C(qxs, q.neg(qys))]
+        rows = slash_row(psi, qlc)
+        out_ = []
+        for c in range(4):
+            out_.append(cmat(q, csum(q, rows[c] + [(psi[c], C(ms))])))
+        qmemo[prefix] = out_
+        return out_
+
+    # momentum sums used in the quark block must live in the quark block's namespace;
+    # they were created in the gluon block (same scope in the emitted code), fine.
+    vspin = [[C(S(name=f'vs[{h}][{j}].re'), S(name=f'vs[{h}][{j}].im')) for j in range(4)] for h in range(2)]
+    amps = [[None] * len(proc.orderings) for _ in range(2)]
+    for si, sigma in enumerate(proc.orderings):
+        terms = [[] for _ in range(4)]
+        for s in range(k):
+            rows = slash_row(Q(sigma[:s]), J(sigma[s:]))
+            for c in range(4):
+                terms[c] += rows[c]
+        full = [cmat(q, csum(q, terms[c])) for c in range(4)]
+        for h in range(2):
+            amps[h][si] = cmat(q, csum(q, [(full[c], vspin[h][c]) for c in range(4)]))
+    quark_flops = q.flops
+    # colour sums (one per antitop helicity)
+    cs = Block('w')
+    csq = []
+    n_or = len(proc.orderings)
+    for h in range(2):
+        A = amps[h]
+        tot_terms = []
+        for i in range(n_or):
+            yr = [(const(proc.cnum[i][i] if j == i else 2 * proc.cnum[i][j]), A[j].re) for j in range(i, n_or)]
+            yi = [(const(proc.cnum[i][i] if j == i else 2 * proc.cnum[i][j]), A[j].im) for j in range(i, n_or)]
+            y_r = cs.sumprod(yr)
+            y_i = cs.sumprod(yi)
+            tot_terms.append((A[i].re, y_r))
+            tot_terms.append((A[i].im, y_i))
+        csq.append(cs.sumprod(tot_terms))
+    colour_flops = cs.flops
+
+    # ---------------- emit ----------------
+    body = []
+    body.append('#pragma unroll 1')
+    body.append(f'for (int gconf = 0; gconf < {2 ** k}; ++gconf) {{')
+    for gi in range(k):
+        body.append(f'    const R lam{gi} = (gconf >> {gi}) & 1 ? R(1) : R(-1);')
+    body += ['    ' + l for l in gluon_lines]
+    body.append('    #pragma unroll 1')
+    body.append('    for (int ht = 0; ht < 2; ++ht) {')
+    body.append('        cplx<R> ubs[4];')
+    body.append('        for (int j = 0; j < 4; ++j) ubs[j] = ht ? ub[1][j] : ub[0][j];')
+    body += ['        ' + l for l in q.lines]
+    if with_colour:
+        body += ['        ' + l for l in cs.lines]
+        body.append(f'        sink.add({cs.ref(csq[0])}, {cs.ref(csq[1])});')
+    else:
+        # expose the amplitudes to the sink (colour contraction done elsewhere)
+        body.append(f'        sink.amplitudes(')
+        for h in range(2):
+            for si in range(n_or):
+                a = amps[h][si]
+                sep = ',' if (h, si) != (1, n_or - 1) else ''
+                body.append(f'            {q.ref(a.re)}, {q.ref(a.im)}{sep}')
+        body.append('        );')
+    body.append('    }')
+    body.append('}')
+    out += ['    ' + l for l in body]
+    out.append('}')
+    if not with_colour:
+        return '\n'.join(out), None
+    out.append('')
+    out.append(f'// normalisation: g^(2k) / (avg * sym * colour denominator)')
+    out.append(f'__host__ __device__ constexpr double {fn}_norm_noalpha() '
+               f'{{ return 1.0 / ({proc.avg!r} * {float(proc.sym)!r} * {float(proc.cden)!r}); }}')
+    out.append(f'constexpr int {fn}_k = {k};')
+    out.append(f'constexpr int {fn}_ncolour = {n_or};')
+    helis = 2 ** (k + 2)
+    flops = dict(gluon_per_gconf=gluon_flops, quark_per_top_hel=quark_flops,
+                 colour_per_hel=colour_flops // 2,
+                 per_event=(2 ** k) * (gluon_flops + 2 * quark_flops + colour_flops),
+                 helicities=helis)
+    out.append(f'// flops per event (generated count): {flops}')
+    return '\n'.join(out), flops
+
+
+def colour_table(proc):
+    return proc.cnum, proc.cden
+
+
+def emit_all(outdir):
+    os.makedirs(outdir, exist_ok=True)
+    summary = {}
+    for name, n_ext in (('gg_tt', 4), ('gg_ttg', 5), ('gg_ttgg', 6)):
+        proc = GGTTProcess(name, n_ext)
+        src, flops = emit_qcd(proc, with_colour=True)
+        src_a, _ = emit_qcd(proc, with_colour=False)
+        src_a = src_a.replace(f'me_{name}_body', f'me_{name}_amps')
+        cnum, cden = proc.cnum, proc.cden
+        ctab = [f'// colour matrix numerators for {name} (denominator {cden})',
+                f'__device__ __constant__ const signed short me_{name}_cnum[{len(cnum)}][{len(cnum)}] = {{']
+        for row in cnum:
+            ctab.append('    {' + ', '.join(str(v) for v in row) + '},')
+        ctab.append('};')
+        ctab.append(f'constexpr int me_{name}_cden = {cden};')
+        with open(os.path.join(outdir, f'me_{name}.inc'), 'w') as f:
+            f.write('// Generated by paper_2211_14056_amd.gen.process_compiler -- do not edit.\n')
+            f.write(src + '\n\n' + src_a + '\n\n' + '\n'.join(ctab) + '\n')
+        summary[name] = flops
+    with open(os.path.join(outdir, 'flops.txt'), 'w') as f:
+        for name, fl in summary.items():
+            f.write(f'{name} {fl}\n')
+    return summary
+
+
+if __name__ == '__main__':
+    import sys
+    print(emit_all(sys.argv[1] if len(sys.argv) > 1 else 'generated'))

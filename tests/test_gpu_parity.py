@@ -1,0 +1,324 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Bars: bit-exact uniforms and bin indices; FP64 momenta/weights/|M|^2 within
+1e-12 relative; FP32 |M|^2 within 1e-5 median and 1e-3 max relative (events
+passing cuts); Vegas sums and refined edges within 1e-12.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2211_14056_amd as mf
+from oracle import (closed_forms, cuts as ocuts, integrand, me_explicit, me_ordered, phase_space as ops,
+                    philox, processes, vegas as ovegas)
+
+pytestmark = pytest.mark.gpu
+
+P = processes.DEFAULT_PARAMS
+PEE = processes.EE_PARAMS
+PROCS = ['ee_mumu', 'gg_tt', 'gg_ttg', 'gg_ttgg']
+
+
+def say(*a):
+    print('[gpu-test]', *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope='module')
+def h():
+    torch.cuda.init()
+    return mf.Handle(0)
+
+
+def prm_of(proc):
+    return mf.params_from_dict(PEE if proc == 'ee_mumu' else P)
+
+
+def par_of(proc):
+    return PEE if proc == 'ee_mumu' else P
+
+
+def gpu_events(h, proc, n, seed, offset=0, edges=None, nb=50):
+    pid = mf.PROCESS[proc]
+    d = mf.mf_process_dims(pid)
+    dev = torch.device('cuda', 0)
+    x_out = torch.empty(d, n, dtype=torch.float64, device=dev)
+    pas = torch.empty(n, dtype=torch.uint8, device=dev)
+    bins = torch.empty(d, n, dtype=torch.int16, device=dev)
+    jac = torch.empty(n, dtype=torch.float64, device=dev)
+    e = None if edges is None else torch.tensor(edges, dtype=torch.float64, device=dev).contiguous()
+    out = mf.mf_phase_space(h, pid, prm_of(proc), n, seed=seed, offset=offset, edges=e, nb=nb,
+                            pass_=pas, bin_idx=bins, jac=jac, x_out=x_out)
+    torch.cuda.synchronize()
+    return out
+
+
+def oracle_momenta(proc, x):
+    """x [d][N] numpy -> p [N, n_ext, 4] torch f64, w [N]."""
+    u = torch.tensor(np.ascontiguousarray(x.T), dtype=torch.float64)
+    return integrand.momenta(proc, par_of(proc), u)
+
+
+def gpu_me(h, proc, p, precision):
+    pid = mf.PROCESS[proc]
+    out = mf.matrix_element(h, pid, p.contiguous(), precision, prm_of(proc))
+    torch.cuda.synchronize()
+    return out.double().cpu().numpy()
+
+
+def oracle_me(proc, p_gpu_layout):
+    """p [n_ext][4][N] numpy -> oracle ME [N]."""
+    p = torch.tensor(np.ascontiguousarray(np.transpose(p_gpu_layout, (2, 0, 1))), dtype=torch.float64)
+    return integrand.me(proc, p, par_of(proc)).numpy()
+
+
+# ------------------------------------------------------------------ a1: RNG
+@pytest.mark.parametrize('proc', PROCS)
+def test_uniforms_bitwise(h, proc):
+    n = 5000 + 37
+    say('uniforms', proc, n)
+    ev = gpu_events(h, proc, n, seed=1234, offset=10 ** 10 + 3)
+    x_ref = philox.uniforms(1234, n, processes.dims(proc), offset=10 ** 10 + 3)
+    assert np.array_equal(ev['x'].cpu().numpy(), x_ref)
+
+
+# ------------------------------------------------------------------ a2-a4: phase space
+@pytest.mark.parametrize('proc', PROCS)
+def test_phase_space_vs_oracle(h, proc):
+    n = 4096 + 17
+    d = processes.dims(proc)
+    rng = np.random.default_rng(5)
+    w_ = rng.uniform(0.3, 1.7, (d, 50))
+    edges = np.concatenate([np.zeros((d, 1)), np.cumsum(w_, 1) / w_.sum(1, keepdims=True)], 1)
+    edges[:, -1] = 1.0
+    say('phase space', proc, n)
+    ev = gpu_events(h, proc, n, seed=77, edges=edges)
+    x = ev['x'].cpu().numpy()
+    y, b, J = ovegas.vegas_map(x, edges)
+    assert np.array_equal(ev['bin_idx'].cpu().numpy().astype(np.int64), b)
+    assert np.allclose(ev['jac'].cpu().numpy(), J, rtol=1e-13, atol=0)
+    p_ref, w_ref = oracle_momenta(proc, y)
+    p_gpu = ev['p'].cpu().numpy()
+    rs = par_of(proc)['sqrt_s']
+    # both sides solve the same root equations (GPU: safeguarded Newton, oracle:
+    # bisection); near rho -> 1 the mass-ratio root is ill-conditioned, so agree
+    # to 1e-12 of sqrt(s) rather than to the last bit
+    diff = np.abs(np.transpose(p_gpu, (2, 0, 1)) - p_ref.numpy()).max() / rs
+    assert diff < 1e-12, diff
+    wr = w_ref.numpy()
+    assert np.abs(ev['w'].cpu().numpy() / wr - 1).max() < 1e-12
+    # cut decisions agree except within rounding of a cut boundary
+    ok_ref = ocuts.passes(p_ref, par_of(proc)).numpy()
+    ok_gpu = ev['pass_'].cpu().numpy().astype(bool)
+    assert (ok_ref != ok_gpu).sum() == 0
+
+
+def test_phase_space_conservation_full_size(h):
+    n = 1_000_000
+    say('phase space full size gg_ttgg', n)
+    ev = gpu_events(h, 'gg_ttgg', n, seed=4)
+    p = ev['p']
+    tot = p[2:].sum(0)
+    assert float((tot[0] - 1000.0).abs().max()) < 1e-12 * 1000
+    assert float(tot[1:].abs().max()) < 1e-12 * 1000
+    m2 = p[:, 0] ** 2 - p[:, 1] ** 2 - p[:, 2] ** 2 - p[:, 3] ** 2
+    assert float(((m2[2:4] - 173.0 ** 2).abs() / p[2:4, 0] ** 2).max()) < 1e-10
+    assert float((m2[4:].abs() / p[4:, 0] ** 2).max()) < 1e-10
+    assert bool(torch.isfinite(ev['w']).all()) and float(ev['w'].min()) > 0
+    assert h.failures() == 0
+
+
+# ------------------------------------------------------------------ a5: matrix element
+ME_N = {'ee_mumu': 2000, 'gg_tt': 2000, 'gg_ttg': 300, 'gg_ttgg': 40}
+
+
+@pytest.mark.parametrize('proc', PROCS)
+def test_me_fp64_vs_oracle(h, proc):
+    n = ME_N[proc] + 3
+    say('me fp64', proc, n)
+    ev = gpu_events(h, proc, n, seed=21)
+    me = gpu_me(h, proc, ev['p'], mf.MF_FP64)
+    ref = oracle_me(proc, ev['p'].cpu().numpy())
+    rel = np.abs(me / ref - 1)
+    say('  max rel', rel.max())
+    assert rel.max() < 1e-12
+
+
+@pytest.mark.parametrize('proc', PROCS)
+def test_me_fp32_vs_oracle(h, proc):
+    n = ME_N[proc] + 3
+    say('me fp32', proc, n)
+    ev = gpu_events(h, proc, n, seed=22)
+    me = gpu_me(h, proc, ev['p'], mf.MF_FP32)
+    ref = oracle_me(proc, ev['p'].cpu().numpy())
+    ok = ev['pass_'].cpu().numpy().astype(bool)
+    rel = np.abs(me / ref - 1)[ok]
+    say('  median', np.median(rel), 'max', rel.max())
+    assert np.median(rel) < 1e-5 and rel.max() < 1e-3
+
+
+def test_me_closed_forms_on_gpu(h):
+    # e+e- -> mu+mu- and gg -> ttbar against their closed forms, per event
+    for proc in ('ee_mumu', 'gg_tt'):
+        n = 10000
+        say('closed form', proc, n)
+        ev = gpu_events(h, proc, n, seed=3)
+        p = ev['p'].cpu().numpy()
+        me = gpu_me(h, proc, ev['p'], mf.MF_FP64)
+        if proc == 'ee_mumu':
+            c = (p[0, 1] * p[2, 1] + p[0, 2] * p[2, 2] + p[0, 3] * p[2, 3]) / (
+                np.sqrt((p[0, 1:] ** 2).sum(0)) * np.sqrt((p[2, 1:] ** 2).sum(0)))
+            ref = (4 * math.pi * PEE['alpha']) ** 2 * (1 + c * c)
+        else:
+            s = P['sqrt_s'] ** 2
+            t1 = 2 * (p[0, 0] * p[2, 0] - (p[0, 1:] * p[2, 1:]).sum(0)) / s
+            ref = np.array([closed_forms.gg_tt_me(float(t), s, P['m_t'], P['alpha_s']) for t in t1])
+        assert np.abs(me / ref - 1).max() < 1e-12
+
+
+@pytest.mark.parametrize('proc,n', [('gg_tt', 1_000_000), ('gg_ttg', 4_000_000), ('gg_ttgg', 1_000_000)])
+def test_me_full_size_sampled(h, proc, n):
+    """At the benchmark batch sizes: all outputs finite and positive, sampled events vs oracle."""
+    say('me full size', proc, n)
+    ev = gpu_events(h, proc, n, seed=1 + mf.PROCESS[proc])
+    for prec in (mf.MF_FP64, mf.MF_FP32):
+        me = mf.matrix_element(h, mf.PROCESS[proc], ev['p'], prec, prm_of(proc))
+        torch.cuda.synchronize()
+        assert bool(torch.isfinite(me).all()) and float(me.min()) > 0
+        idx = torch.tensor(np.random.default_rng(9).choice(n, 24, replace=False), device=me.device)
+        idx = torch.cat([idx, torch.tensor([0, n - 1], device=me.device)])
+        ps = ev['p'][:, :, idx].cpu().numpy()
+        ref = oracle_me(proc, ps)
+        got = me[idx].double().cpu().numpy()
+        rel = np.abs(got / ref - 1)
+        ok = ev['pass_'][idx].cpu().numpy().astype(bool)
+        if prec == mf.MF_FP64:
+            assert rel.max() < 1e-12
+        else:
+            assert rel[ok].max() < 1e-3
+
+
+def test_me_lorentz_invariance_fp64(h):
+    n = 512
+    say('lorentz gg_ttgg', n)
+    ev = gpu_events(h, 'gg_ttgg', n, seed=8)
+    p = ev['p']
+    a = mf.matrix_element(h, mf.MF_GG_TTGG, p, mf.MF_FP64)
+    # boost along z (the kernel takes the beams along the z axis), beta = 0.6
+    beta = 0.6
+    g = 1 / math.sqrt(1 - beta * beta)
+    q = p.clone()
+    q[:, 0] = g * (p[:, 0] + beta * p[:, 3])
+    q[:, 3] = g * (p[:, 3] + beta * p[:, 0])
+    b = mf.matrix_element(h, mf.MF_GG_TTGG, q.contiguous(), mf.MF_FP64)
+    torch.cuda.synchronize()
+    # the boost rounds the momenta (1e-16 relative), which near-singular events
+    # amplify by their condition number (up to ~1e4 here)
+    rel = ((a / b) - 1).abs()
+    assert float(rel.max()) < 1e-10 and float(rel.median()) < 1e-13
+
+
+def test_me_empty_and_tiny_batches(h):
+    for n in (0, 1, 63, 65):
+        say('tiny batch', n)
+        p = torch.empty(6, 4, n, dtype=torch.float64, device='cuda')
+        if n:
+            ev = gpu_events(h, 'gg_ttgg', n, seed=2)
+            p = ev['p']
+        me = mf.matrix_element(h, mf.MF_GG_TTGG, p, mf.MF_FP64)
+        torch.cuda.synchronize()
+        assert me.shape == (n,)
+        if n:
+            ref = oracle_me('gg_ttgg', p.cpu().numpy())
+            assert np.abs(me.cpu().numpy() / ref - 1).max() < 1e-12
+
+
+# ------------------------------------------------------------------ a7-a8: Vegas
+def test_vegas_refine_vs_oracle(h):
+    proc = 'gg_ttg'
+    n = 20000 + 11
+    d = processes.dims(proc)
+    say('vegas refine', proc, n)
+    ev = gpu_events(h, proc, n, seed=31, edges=ovegas.uniform_grid(d, 50))
+    me = mf.matrix_element(h, mf.PROCESS[proc], ev['p'], mf.MF_FP64, prm_of(proc))
+    dev = me.device
+    edges = torch.tensor(ovegas.uniform_grid(d, 50), dtype=torch.float64, device=dev).contiguous()
+    acc = torch.empty(2 + d * 50, dtype=torch.float64, device=dev)
+    F = torch.empty(n, dtype=torch.float64, device=dev)
+    mf.mf_vegas_refine(h, prm_of(proc), n, d, 50, 1.5, ev['w'], ev['jac'], me, ev['pass_'], ev['bin_idx'],
+                       acc, edges, F=F)
+    torch.cuda.synchronize()
+    s = P['sqrt_s'] ** 2
+    F_ref = closed_forms.GEV2_TO_PB * ev['w'].cpu().numpy() * me.cpu().numpy() / (2 * s) * \
+        ev['pass_'].cpu().numpy() * ev['jac'].cpu().numpy()
+    assert np.abs(F.cpu().numpy() - F_ref).max() <= 1e-13 * np.abs(F_ref).max()
+    sf, sf2, hist = ovegas.accumulate(F_ref, ev['bin_idx'].cpu().numpy().astype(np.int64), 50)
+    a = acc.cpu().numpy()
+    assert abs(a[0] / sf - 1) < 1e-12 and abs(a[1] / sf2 - 1) < 1e-12
+    assert np.abs(a[2:].reshape(d, 50) - hist).max() <= 1e-12 * hist.max()
+    new_ref = ovegas.refine(ovegas.uniform_grid(d, 50), hist, 1.5)
+    assert np.abs(edges.cpu().numpy() - new_ref).max() < 1e-12
+
+
+def test_vegas_deterministic(h):
+    proc = 'gg_tt'
+    n = 300000
+    say('vegas determinism', n)
+    ev = gpu_events(h, proc, n, seed=5)
+    me = mf.matrix_element(h, mf.PROCESS[proc], ev['p'], mf.MF_FP64, prm_of(proc))
+    outs = []
+    for _ in range(2):
+        edges = torch.tensor(ovegas.uniform_grid(2, 50), dtype=torch.float64, device='cuda').contiguous()
+        acc = torch.empty(2 + 100, dtype=torch.float64, device='cuda')
+        mf.mf_vegas_refine(h, prm_of(proc), n, 2, 50, 1.5, ev['w'], ev['jac'], me, ev['pass_'],
+                           ev['bin_idx'], acc, edges)
+        torch.cuda.synchronize()
+        outs.append((acc.cpu().numpy(), edges.cpu().numpy()))
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
+def _gpu_vegas(h, proc, n, iters, seed, precision=mf.MF_FP64):
+    pid = mf.PROCESS[proc]
+    d = processes.dims(proc)
+    dev = torch.device('cuda', 0)
+    edges = torch.tensor(ovegas.uniform_grid(d, 50), dtype=torch.float64, device=dev).contiguous()
+    acc = torch.empty(2 + d * 50, dtype=torch.float64, device=dev)
+    Is, vs = [], []
+    for it in range(iters):
+        ev = mf.mf_phase_space(h, pid, prm_of(proc), n, seed=seed, offset=it * n, edges=edges, nb=50,
+                               pass_=torch.empty(n, dtype=torch.uint8, device=dev),
+                               bin_idx=torch.empty(d, n, dtype=torch.int16, device=dev),
+                               jac=torch.empty(n, dtype=torch.float64, device=dev))
+        me = mf.matrix_element(h, pid, ev['p'], precision, prm_of(proc))
+        mf.mf_vegas_refine(h, prm_of(proc), n, d, 50, 1.5, ev['w'], ev['jac'], me, ev['pass_'],
+                           ev['bin_idx'], acc, edges)
+        a = acc.cpu().numpy()
+        I, v = ovegas.estimate(a[0], a[1], n)
+        Is.append(I)
+        vs.append(v)
+    return ovegas.combine(Is, vs), Is, vs, edges.cpu().numpy()
+
+
+def test_vegas_ee_mumu_matches_oracle_and_closed_form(h):
+    n, iters = 100_000, 5
+    say('vegas ee_mumu', n, iters)
+    (I, sig, chi2), Is, vs, edges = _gpu_vegas(h, 'ee_mumu', n, iters, seed=1)
+    f = lambda y: integrand.integrand('ee_mumu', PEE, y)[0]
+    I_o, sig_o, chi2_o, its, edges_o = ovegas.integrate(f, 2, n, iters, seed=1)
+    assert abs(I / I_o - 1) < 1e-12
+    assert np.abs(edges - edges_o).max() < 1e-10
+    ref = closed_forms.ee_mumu_sigma(PEE['sqrt_s'] ** 2, PEE['alpha']) * closed_forms.GEV2_TO_PB
+    say('  sigma', I, '+-', sig, 'closed form', ref)
+    assert abs(I - ref) < 3 * sig
+
+
+def test_vegas_gg_tt_closed_form(h):
+    n, iters = 1_000_000, 5
+    say('vegas gg_tt', n, iters)
+    (I, sig, chi2), Is, vs, edges = _gpu_vegas(h, 'gg_tt', n, iters, seed=2)
+    ref = closed_forms.gg_tt_sigma(P['sqrt_s'] ** 2, P['m_t'], P['alpha_s']) * closed_forms.GEV2_TO_PB
+    say('  sigma', I, '+-', sig, 'closed form', ref)
+    assert abs(I - ref) < 3 * sig

@@ -157,3 +157,16 @@ def test_mass_ratio_solver_inverts_cdf():
         r = ps._mass_ratio(u, a)
         back = (a + 1) * r ** (2 * a) - a * r ** (2 * (a + 1))
         assert (back - u).abs().max() < 1e-14
+
+
+def test_conservation_for_strongly_boosted_light_subsystem():
+    # tiny intermediate-mass uniforms give a light, strongly boosted remainder
+    # system; momentum must still balance to FP64 rounding
+    n = 4
+    u = torch.tensor(philox.uniforms(6, 64, 3 * n - 4).T.copy())
+    u[:, 0] = 0.5
+    u[:, 1] = torch.logspace(-14, -4, 64, dtype=torch.float64)
+    p, w = ps.phase_space(u, SQRT_S, [MT, MT, 0.0, 0.0])
+    tot = p.sum(1)
+    assert (tot[:, 0] - SQRT_S).abs().max() < 1e-12 * SQRT_S
+    assert tot[:, 1:].abs().max() < 1e-12 * SQRT_S
