@@ -159,18 +159,26 @@ mf_status mf_matrix_element_vjp(mf_handle h, const mf_request* reqs, int n_reqs,
  * mf_vegas_refine -- rows a7 and a8: forms F = flux * w * jac * me * pass with
  * flux = (hbar c)^2 / (2 s) in pb GeV^2 / GeV^2 (so F is in pb), reduces
  * acc[0] = sum F, acc[1] = sum F^2, acc[2 + k*nb + i] = sum of F^2 over events
- * in bin i of dimension k (deterministic order), and, if update_edges != 0,
- * refines `edges` in place (Lepage: smoothing, damping exponent alpha,
- * rebinning).  If rng_counter is not NULL, *rng_counter += n on the device.
+ * in bin i of dimension k (deterministic order).  flags:
+ *   MF_VEGAS_ACCUMULATE  add this batch's sums to acc instead of overwriting it
+ *                        (several batches per Vegas iteration);
+ *   MF_VEGAS_REFINE      then refine `edges` in place from acc (Lepage:
+ *                        smoothing, damping exponent alpha, rebinning).
+ * If rng_counter is not NULL, *rng_counter += n on the device.
  *   w, me      [n] required (me is f32 when me_f32 != 0); jac, pass optional;
  *   bin_idx    [d][n] required; F [n] optional output; acc [2 + d*nb] out.
  * Errors: MF_ERR_INVALID_ARG for d < 1 or d > 8, nb < 2 or nb > 64, n < 0,
  * or a NULL required pointer; MF_ERR_NO_MEMORY if workspace cannot grow.
  */
+enum { MF_VEGAS_REFINE = 1, MF_VEGAS_ACCUMULATE = 2 };
+
 mf_status mf_vegas_refine(mf_handle h, const mf_params* prm, int64_t n, int d, int nb, double alpha,
                           const double* w, const double* jac, const void* me, int me_f32,
                           const uint8_t* pass, const int16_t* bin_idx, double* F, double* acc,
-                          double* edges, int update_edges, uint64_t* rng_counter, void* stream);
+                          double* edges, int flags, uint64_t* rng_counter, void* stream);
+
+/* 1 if this build serves matrix elements at `precision`, else 0. */
+int mf_precision_available(int precision);
 
 #ifdef __cplusplus
 }

@@ -60,6 +60,7 @@ def lib():
     L.mf_failures.argtypes = [VP, ctypes.POINTER(U64)]
     L.mf_process_legs.argtypes = [I32]
     L.mf_process_dims.argtypes = [I32]
+    L.mf_precision_available.argtypes = [I32]
     L.mf_phase_space.argtypes = [VP, I32, ctypes.POINTER(mf_params), I64, VP, U64, U64, VP, VP, I32,
                                  VP, VP, VP, VP, VP, VP, VP]
     L.mf_matrix_element.argtypes = [VP, ctypes.POINTER(mf_request), I32, I32, ctypes.POINTER(mf_params), VP]
@@ -221,8 +222,18 @@ def mf_matrix_element_vjp(h, reqs, precision, prm, edges=None, nb=50, stream=Non
                                        _stream(stream)))
 
 
+MF_VEGAS_REFINE, MF_VEGAS_ACCUMULATE = 1, 2
+
+
+def mf_precision_available(precision):
+    return bool(lib().mf_precision_available(precision))
+
+
+has_precision = mf_precision_available
+
+
 def mf_vegas_refine(h, prm, n, d, nb, alpha, w, jac, me, pass_, bin_idx, acc, edges, F=None,
-                    update_edges=True, rng_counter=None, stream=None):
+                    update_edges=True, accumulate=False, rng_counter=None, stream=None):
     me_f32 = 1 if me.dtype == torch.float32 else 0
     _need(w, n, 'w', torch.float64)
     _need(jac, n, 'jac', torch.float64)
@@ -235,7 +246,9 @@ def mf_vegas_refine(h, prm, n, d, nb, alpha, w, jac, me, pass_, bin_idx, acc, ed
     _need(rng_counter, 1, 'rng_counter', torch.int64)
     _check(lib().mf_vegas_refine(h.h, ctypes.byref(prm), n, d, nb, alpha, _ptr(w), _ptr(jac), _ptr(me), me_f32,
                                  _ptr(pass_), _ptr(bin_idx), _ptr(F), _ptr(acc), _ptr(edges),
-                                 1 if update_edges else 0, _ptr(rng_counter), _stream(stream)))
+                                 (MF_VEGAS_REFINE if update_edges else 0)
+                                 | (MF_VEGAS_ACCUMULATE if accumulate else 0),
+                                 _ptr(rng_counter), _stream(stream)))
 
 
 def matrix_element(h, proc, p, precision=MF_FP64, prm=None, stream=None):

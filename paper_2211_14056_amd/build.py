@@ -15,7 +15,8 @@ GEN = os.path.join(CSRC, 'generated')
 OUT = os.path.join(HERE, 'libmfhip.so')
 BUILD = os.path.join(HERE, '_build')
 
-SOURCES = ['mf_api.cpp', 'phase_space.hip', 'me_kernels.hip', 'me_mfma.hip', 'me_vjp.hip', 'vegas.hip']
+SOURCES = ['me_vjp_ttgg_f64.hip', 'me_vjp_ttgg_f32.hip', 'me_vjp_small.hip', 'me_kernels.hip', 'me_mfma.hip',
+           'mf_api.cpp', 'phase_space.hip', 'me_vjp.hip', 'vegas.hip']
 
 FLAGS = ['--offload-arch=gfx950', '-O3', '-std=c++17', '-fPIC', '-ffp-contract=fast',
          # no packed FP32 arithmetic anywhere in device code
@@ -36,8 +37,22 @@ def generate():
     return process_compiler.emit_all(GEN)
 
 
-def compile_one(src, extra=()):
+def _newest_input():
+    newest = 0.0
+    for d in (CSRC, GEN, os.path.join(os.path.dirname(HERE), 'include')):
+        for f in os.listdir(d):
+            p = os.path.join(d, f)
+            if os.path.isfile(p):
+                newest = max(newest, os.path.getmtime(p))
+    return newest
+
+
+def compile_one(src, extra=(), incremental=False):
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + '.o')
+    if incremental and os.path.exists(obj) and os.path.getmtime(obj) >= max(
+            _newest_input() if src.endswith('.cpp') else os.path.getmtime(os.path.join(CSRC, src)),
+            _newest_header()):
+        return obj
     cmd = [hipcc()] + FLAGS + list(extra) + ['-c', os.path.join(CSRC, src), '-o', obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
@@ -45,13 +60,37 @@ def compile_one(src, extra=()):
     return obj
 
 
-def build(jobs=None, verbose=True):
+def _newest_header():
+    newest = 0.0
+    for d in (CSRC, GEN, os.path.join(os.path.dirname(HERE), 'include')):
+        for f in os.listdir(d):
+            if f.endswith(('.h', '.inc')):
+                newest = max(newest, os.path.getmtime(os.path.join(d, f)))
+    return newest
+
+
+def build(jobs=None, verbose=True, incremental=False):
+    """Generate and compile everything (incremental=True skips up-to-date objects)."""
     os.makedirs(BUILD, exist_ok=True)
-    generate()
+    if incremental and os.path.isdir(GEN):
+        # regenerate into a scratch copy; keep file times when the text is unchanged
+        import filecmp
+        import tempfile
+        tmp = tempfile.mkdtemp()
+        sys.path.insert(0, os.path.dirname(HERE))
+        from paper_2211_14056_amd.gen import process_compiler
+        process_compiler.emit_all(tmp)
+        for f in os.listdir(tmp):
+            dst = os.path.join(GEN, f)
+            if not (os.path.exists(dst) and filecmp.cmp(os.path.join(tmp, f), dst, shallow=False)):
+                shutil.copy(os.path.join(tmp, f), dst)
+        shutil.rmtree(tmp)
+    else:
+        generate()
     srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
     jobs = jobs or min(len(srcs), max(1, (os.cpu_count() or 4)))
     with cf.ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(compile_one, srcs))
+        objs = list(ex.map(lambda s: compile_one(s, incremental=incremental), srcs))
     tmp = OUT + '.tmp'
     cmd = [hipcc(), '--offload-arch=gfx950', '-shared', '-fPIC'] + objs + ['-o', tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -66,5 +105,6 @@ def build(jobs=None, verbose=True):
 if __name__ == '__main__':
     ap = argparse.ArgumentParser()
     ap.add_argument('--jobs', type=int, default=None)
+    ap.add_argument('--incremental', action='store_true')
     args = ap.parse_args()
-    build(args.jobs)
+    build(args.jobs, incremental=args.incremental)

@@ -44,6 +44,28 @@ struct MeJob {
 //            3 = FP32 amplitudes + FP32 MFMA colour
 hipError_t launch_matrix_element(const MeJob& j, int precision, double mt, double alpha_s,
                                  double alpha, int block, hipStream_t s);
+bool precision_available(int precision);
+// precisions 2 and 3 (matrix-core colour contraction), gg processes only;
+// `coupling` = (4 pi alpha_s)^k
+hipError_t launch_matrix_element_mfma(const MeJob& j, int precision, double mt, double coupling, int block,
+                                      hipStream_t s);
+
+struct VjpJob {
+    int proc;
+    int64_t n;
+    const double* x;            // [d][n]
+    const double* grad_me;      // [n]
+    double* grad_x;             // [d][n]
+    double* grad_theta;         // [n][2]
+    void* me_out;               // [n] or null
+    int me_f32;
+    const double* edges;        // [d][nb+1] or null
+    int nb;
+    double sqrt_s, mt, alpha_s, coupling;
+};
+
+// precision 0: FP64 recursion; otherwise FP32 recursion (kinematics FP64)
+hipError_t launch_vjp(const VjpJob& j, int precision, hipStream_t s);
 
 struct VegasArgs {
     int64_t n;
@@ -61,6 +83,7 @@ struct VegasArgs {
     double* acc;                // [2 + d*nb]
     double* edges;              // [d][nb+1]
     int update_edges;
+    int accumulate;             // acc += batch sums instead of acc = batch sums
     uint64_t* rng_counter;      // may be null
 };
 

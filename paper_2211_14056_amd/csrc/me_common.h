@@ -4,11 +4,14 @@
 // matrix element from such external-state routines plus vertices and
 // propagators (sect. 2, Fig. 2); it does not print their form.
 //
-// All wavefunctions are evaluated from FP64 momenta in FP64 and rounded once
-// to the kernel's working type R.
+// All wavefunctions are evaluated in the kinematic type KT (double, or
+// Dual<double> in the derivative kernel) and rounded once to the kernel's
+// working type R.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include "dual.h"
 
 template <typename R>
 struct cplx {
@@ -19,89 +22,91 @@ struct cplx {
 //   chi_+ = (|p|+pz, px + i py)/sqrt(2|p|(|p|+pz)),  chi_- = (-px + i py, |p|+pz)/(same)
 // with |p|+pz evaluated as pT^2/(|p|-pz) when pz < 0 (no cancellation), the
 // limits chi_+ = (0,1), chi_- = (-1,0) for p along -z, and chi along +z at rest.
-__device__ __forceinline__ void helicity_chi(const double* p, int lam, double c[4])
+template <typename KT>
+__device__ __forceinline__ void helicity_chi(const KT* p, int lam, KT c[4])
 {
-    const double px = p[1], py = p[2], pz = p[3];
-    const double pt2 = px * px + py * py;
-    const double pa = sqrt(pt2 + pz * pz);
-    const double s = (pz >= 0.0) ? pa + pz : pt2 / (pa - pz);
-    if (pa == 0.0) {
-        c[0] = lam > 0 ? 1.0 : 0.0; c[1] = 0.0;
-        c[2] = lam > 0 ? 0.0 : 1.0; c[3] = 0.0;
+    const KT px = p[1], py = p[2], pz = p[3];
+    const KT pt2 = px * px + py * py;
+    const KT pa = sqrt(pt2 + pz * pz);
+    if (kval(pa) == 0.0) {
+        c[0] = KT(lam > 0 ? 1.0 : 0.0); c[1] = KT(0.0);
+        c[2] = KT(lam > 0 ? 0.0 : 1.0); c[3] = KT(0.0);
         return;
     }
-    if (s == 0.0) {
-        c[0] = lam > 0 ? 0.0 : -1.0; c[1] = 0.0;
-        c[2] = lam > 0 ? 1.0 : 0.0;  c[3] = 0.0;
+    const KT s = (kval(pz) >= 0.0) ? pa + pz : pt2 / (pa - pz);
+    if (kval(s) == 0.0) {
+        c[0] = KT(lam > 0 ? 0.0 : -1.0); c[1] = KT(0.0);
+        c[2] = KT(lam > 0 ? 1.0 : 0.0);  c[3] = KT(0.0);
         return;
     }
-    const double inv = 1.0 / sqrt(2.0 * pa * s);
+    const KT inv = KT(1.0) / sqrt(KT(2.0) * pa * s);
     if (lam > 0) {
-        c[0] = s * inv;   c[1] = 0.0;
+        c[0] = s * inv;   c[1] = KT(0.0);
         c[2] = px * inv;  c[3] = py * inv;
     } else {
         c[0] = -px * inv; c[1] = py * inv;
-        c[2] = s * inv;   c[3] = 0.0;
+        c[2] = s * inv;   c[3] = KT(0.0);
     }
 }
 
 // omega_+ = sqrt(E + |p|), omega_- = m / omega_+ (= sqrt(E - |p|) on shell).
-__device__ __forceinline__ void omegas(const double* p, double m, double& wp, double& wm)
+template <typename KT>
+__device__ __forceinline__ void omegas(const KT* p, KT m, KT& wp, KT& wm)
 {
-    const double pa = sqrt(p[1] * p[1] + p[2] * p[2] + p[3] * p[3]);
+    const KT pa = sqrt(p[1] * p[1] + p[2] * p[2] + p[3] * p[3]);
     wp = sqrt(p[0] + pa);
     wm = m / wp;
 }
 
 // Row spinor ubar(p, lam) = u^dagger gamma^0 with u = (w_{-lam} chi, w_{lam} chi):
 //   ubar = (w_{lam} chi^*, w_{-lam} chi^*).
-template <typename R>
-__device__ __forceinline__ void ubar_spinor(const double* p, double m, int lam, cplx<R> out[4])
+template <typename R, typename KT>
+__device__ __forceinline__ void ubar_spinor(const KT* p, KT m, int lam, cplx<R> out[4])
 {
-    double c[4], wp, wm;
+    KT c[4], wp, wm;
     helicity_chi(p, lam, c);
     omegas(p, m, wp, wm);
-    const double a = lam > 0 ? wp : wm;   // w_{lam}
-    const double b = lam > 0 ? wm : wp;   // w_{-lam}
-    out[0] = {R(a * c[0]), R(-a * c[1])};
-    out[1] = {R(a * c[2]), R(-a * c[3])};
-    out[2] = {R(b * c[0]), R(-b * c[1])};
-    out[3] = {R(b * c[2]), R(-b * c[3])};
+    const KT a = lam > 0 ? wp : wm;   // w_{lam}
+    const KT b = lam > 0 ? wm : wp;   // w_{-lam}
+    out[0] = {cvt<R>(a * c[0]), cvt<R>(-a * c[1])};
+    out[1] = {cvt<R>(a * c[2]), cvt<R>(-a * c[3])};
+    out[2] = {cvt<R>(b * c[0]), cvt<R>(-b * c[1])};
+    out[3] = {cvt<R>(b * c[2]), cvt<R>(-b * c[3])};
 }
 
 // Column spinor u(p, lam) = (w_{-lam} chi_lam, w_{lam} chi_lam).
-template <typename R>
-__device__ __forceinline__ void u_spinor(const double* p, double m, int lam, cplx<R> out[4])
+template <typename R, typename KT>
+__device__ __forceinline__ void u_spinor(const KT* p, KT m, int lam, cplx<R> out[4])
 {
-    double c[4], wp, wm;
+    KT c[4], wp, wm;
     helicity_chi(p, lam, c);
     omegas(p, m, wp, wm);
-    const double a = lam > 0 ? wm : wp;   // w_{-lam}
-    const double b = lam > 0 ? wp : wm;   // w_{lam}
-    out[0] = {R(a * c[0]), R(a * c[1])};
-    out[1] = {R(a * c[2]), R(a * c[3])};
-    out[2] = {R(b * c[0]), R(b * c[1])};
-    out[3] = {R(b * c[2]), R(b * c[3])};
+    const KT a = lam > 0 ? wm : wp;   // w_{-lam}
+    const KT b = lam > 0 ? wp : wm;   // w_{lam}
+    out[0] = {cvt<R>(a * c[0]), cvt<R>(a * c[1])};
+    out[1] = {cvt<R>(a * c[2]), cvt<R>(a * c[3])};
+    out[2] = {cvt<R>(b * c[0]), cvt<R>(b * c[1])};
+    out[3] = {cvt<R>(b * c[2]), cvt<R>(b * c[3])};
 }
 
 // Column spinor v(p, lam) = (-lam w_{lam} chi_{-lam}, lam w_{-lam} chi_{-lam}).
-template <typename R>
-__device__ __forceinline__ void v_spinor(const double* p, double m, int lam, cplx<R> out[4])
+template <typename R, typename KT>
+__device__ __forceinline__ void v_spinor(const KT* p, KT m, int lam, cplx<R> out[4])
 {
-    double c[4], wp, wm;
+    KT c[4], wp, wm;
     helicity_chi(p, -lam, c);
     omegas(p, m, wp, wm);
-    const double a = -lam * (lam > 0 ? wp : wm);   // -lam w_{lam}
-    const double b = lam * (lam > 0 ? wm : wp);    //  lam w_{-lam}
-    out[0] = {R(a * c[0]), R(a * c[1])};
-    out[1] = {R(a * c[2]), R(a * c[3])};
-    out[2] = {R(b * c[0]), R(b * c[1])};
-    out[3] = {R(b * c[2]), R(b * c[3])};
+    const KT a = double(-lam) * (lam > 0 ? wp : wm);   // -lam w_{lam}
+    const KT b = double(lam) * (lam > 0 ? wm : wp);    //  lam w_{-lam}
+    out[0] = {cvt<R>(a * c[0]), cvt<R>(a * c[1])};
+    out[1] = {cvt<R>(a * c[2]), cvt<R>(a * c[3])};
+    out[2] = {cvt<R>(b * c[0]), cvt<R>(b * c[1])};
+    out[3] = {cvt<R>(b * c[2]), cvt<R>(b * c[3])};
 }
 
 // Row spinor vbar(p, lam) = v^dagger gamma^0.
-template <typename R>
-__device__ __forceinline__ void vbar_spinor(const double* p, double m, int lam, cplx<R> out[4])
+template <typename R, typename KT>
+__device__ __forceinline__ void vbar_spinor(const KT* p, KT m, int lam, cplx<R> out[4])
 {
     cplx<R> v[4];
     v_spinor<R>(p, m, lam, v);
@@ -115,21 +120,22 @@ __device__ __forceinline__ void vbar_spinor(const double* p, double m, int lam, 
 //   u = e1/sqrt2 = (cos th cos ph, cos th sin ph, -sin th)/sqrt2
 //   w = e2/sqrt2 = (-sin ph, cos ph, 0)/sqrt2            (phi = 0 when pT = 0)
 // so that eps(k, l) = -l u - i w and eps*(k, l) = -l u + i w.
-template <typename R>
-__device__ __forceinline__ void pol_basis(const double* k, R u[3], R w[2])
+template <typename R, typename KT>
+__device__ __forceinline__ void pol_basis(const KT* k, R u[3], R w[2])
 {
-    const double kx = k[1], ky = k[2], kz = k[3];
-    const double kt = sqrt(kx * kx + ky * ky);
-    const double ka = sqrt(kt * kt + kz * kz);
-    const double cph = kt > 0.0 ? kx / kt : 1.0;
-    const double sph = kt > 0.0 ? ky / kt : 0.0;
-    const double cth = kz / ka, sth = kt / ka;
+    const KT kx = k[1], ky = k[2], kz = k[3];
+    const KT kt = sqrt(kx * kx + ky * ky);
+    const KT ka = sqrt(kt * kt + kz * kz);
+    const bool has_t = kval(kt) > 0.0;
+    const KT cph = has_t ? kx / kt : KT(1.0);
+    const KT sph = has_t ? ky / kt : KT(0.0);
+    const KT cth = kz / ka, sth = kt / ka;
     const double r = 0.70710678118654752440;
-    u[0] = R(r * cth * cph);
-    u[1] = R(r * cth * sph);
-    u[2] = R(-r * sth);
-    w[0] = R(-r * sph);
-    w[1] = R(r * cph);
+    u[0] = cvt<R>(r * cth * cph);
+    u[1] = cvt<R>(r * cth * sph);
+    u[2] = cvt<R>(-r * sth);
+    w[0] = cvt<R>(-r * sph);
+    w[1] = cvt<R>(r * cph);
 }
 
 // Helicity-sum accumulator used by the VALU colour path.

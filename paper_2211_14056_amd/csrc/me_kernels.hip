@@ -135,6 +135,8 @@ hipError_t launch_valu(const MeJob& j, double mt, double coupling, int block, hi
 
 }  // namespace
 
+bool precision_available(int precision) { return precision >= 0 && precision <= 3; }
+
 hipError_t launch_matrix_element(const MeJob& j, int precision, double mt, double alpha_s, double alpha,
                                  int block, hipStream_t s)
 {
@@ -150,6 +152,10 @@ hipError_t launch_matrix_element(const MeJob& j, int precision, double mt, doubl
     switch (precision) {
     case 0: return launch_valu<double>(j, mt, coupling, block, s);
     case 1: return launch_valu<float>(j, mt, coupling, block, s);
+    case 2:
+    case 3:
+        if (j.proc == EE_MUMU) return hipErrorInvalidValue;    // no colour to contract
+        return launch_matrix_element_mfma(j, precision, mt, coupling, block, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -1,0 +1,202 @@
+// Matrix element with the colour contraction on the matrix cores.
+//
+// Per event and helicity the colour-summed square is a quadratic form in the
+// colour-ordered partial amplitudes, |M|^2_h = Re(A^dagger C A) = a^T C' a + b^T C' b
+// (a, b the real and imaginary parts, C' = den * C an integer matrix, exact
+// in FP32 and in BF16).  Batched over events this is a dense contraction
+// D = C' V with one column of V per (event, helicity, re/im), followed by the
+// column dot products v . D -- the only place in the path where matrix cores
+// apply.
+//
+// Layout.  Each lane of a wave64 owns the amplitude vectors of its event
+// (32 colour slots, ordering index s < NC, zero padding above).  A 32x32
+// MFMA takes a column from two lanes: slots 0..15 from lane n and slots
+// 16..31 from lane n+32.  One v_permlane32_swap per slot pair (j, 16+j)
+// exchanges the upper half of the low lanes' vectors with the lower half of
+// the high lanes' vectors, after which every lane holds the B operand for two
+// 32-column MFMA sets: set A = vectors of lanes 0..31, set B = lanes 32..63.
+// The colour slots are laid out so that the rows of D a lane receives belong
+// to the same 16 slots as the K entries it supplied, so v . D is a 16-term
+// local dot product plus one more swap to add the two halves.  No LDS, no
+// shuffles through memory.
+//
+// Modes: FP32 MFMA (32x32x2, K = 32 in 16 instructions per set) and BF16
+// MFMA (32x32x16, amplitudes split into hi + mid + lo BF16 terms, colour
+// matrix exact in BF16), both accumulating in FP32.
+#include "internal.h"
+#include "me_common.h"
+
+#include "generated/me_gg_tt.inc"
+#include "generated/me_gg_ttg.inc"
+#include "generated/me_gg_ttgg.inc"
+
+namespace mf {
+namespace {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+constexpr double kPi = 3.141592653589793238463;
+
+// Slot held in accumulator row t (t = 4 i + jj) of a lane in half hb:
+// MFMA output row r = 8 i + 4 hb + jj  <->  colour slot 16 hb + t.
+__device__ __forceinline__ int slot_of_row(int r) { return 16 * ((r >> 2) & 1) + 4 * (r >> 3) + (r & 3); }
+
+__device__ __forceinline__ void swap_halves(float& lo_keep, float& hi_keep)
+{
+    // lanes 32..63 of the first operand <-> lanes 0..31 of the second
+    auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(lo_keep), __float_as_uint(hi_keep), false, false);
+    lo_keep = __uint_as_float(r[0]);
+    hi_keep = __uint_as_float(r[1]);
+}
+
+template <int NC, int MODE>   // MODE 0: FP32 MFMA, 1: BF16 x3 MFMA
+struct MfmaColour {
+    static_assert(NC <= 32, "colour orderings must fit 32 slots");
+    float a[2][NC][2];        // [antitop helicity][ordering][re, im], filled by the generated body
+    float acc = 0.0f;         // this lane's helicity sum
+    float cA[16];             // colour numerators in A-operand layout (FP32 mode)
+    bf16x8 cB[2];             // same, BF16 mode: chunk c, element e
+
+    __device__ __forceinline__ void init(const short (*cnum)[NC])
+    {
+        const int lane = threadIdx.x & 63, hb = lane >> 5;
+        const int sr = slot_of_row(lane & 31);
+        if constexpr (MODE == 0) {
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const int sc = 16 * hb + j;
+                cA[j] = (sr < NC && sc < NC) ? (float)cnum[sr][sc] : 0.0f;
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int sc = 16 * hb + 8 * c + e;
+                    cB[c][e] = (__bf16)((sr < NC && sc < NC) ? (float)cnum[sr][sc] : 0.0f);
+                }
+        }
+    }
+
+    __device__ __forceinline__ void flush()
+    {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+#pragma unroll
+            for (int part = 0; part < 2; ++part) {
+                float R1[16], R2[16];
+#pragma unroll
+                for (int j = 0; j < 16; ++j) {
+                    R1[j] = (j < NC) ? a[h][j][part] : 0.0f;
+                    R2[j] = (16 + j < NC) ? a[h][16 + j][part] : 0.0f;
+                    swap_halves(R1[j], R2[j]);
+                }
+                floatx16 DA = {0}, DB = {0};
+                if constexpr (MODE == 0) {
+#pragma unroll
+                    for (int j = 0; j < 16; ++j) {
+                        DA = __builtin_amdgcn_mfma_f32_32x32x2f32(cA[j], R1[j], DA, 0, 0, 0);
+                        DB = __builtin_amdgcn_mfma_f32_32x32x2f32(cA[j], R2[j], DB, 0, 0, 0);
+                    }
+                } else {
+#pragma unroll
+                    for (int c = 0; c < 2; ++c) {
+                        bf16x8 hA, mA, lA, hB, mB, lB;
+#pragma unroll
+                        for (int e = 0; e < 8; ++e) {
+                            const float va = R1[8 * c + e], vb = R2[8 * c + e];
+                            const __bf16 ha = (__bf16)va, hbv = (__bf16)vb;
+                            const float ra = va - (float)ha, rb = vb - (float)hbv;
+                            const __bf16 ma = (__bf16)ra, mb = (__bf16)rb;
+                            hA[e] = ha; mA[e] = ma; lA[e] = (__bf16)(ra - (float)ma);
+                            hB[e] = hbv; mB[e] = mb; lB[e] = (__bf16)(rb - (float)mb);
+                        }
+                        DA = __builtin_amdgcn_mfma_f32_32x32x16_bf16(cB[c], lA, DA, 0, 0, 0);
+                        DA = __builtin_amdgcn_mfma_f32_32x32x16_bf16(cB[c], mA, DA, 0, 0, 0);
+                        DA = __builtin_amdgcn_mfma_f32_32x32x16_bf16(cB[c], hA, DA, 0, 0, 0);
+                        DB = __builtin_amdgcn_mfma_f32_32x32x16_bf16(cB[c], lB, DB, 0, 0, 0);
+                        DB = __builtin_amdgcn_mfma_f32_32x32x16_bf16(cB[c], mB, DB, 0, 0, 0);
+                        DB = __builtin_amdgcn_mfma_f32_32x32x16_bf16(cB[c], hB, DB, 0, 0, 0);
+                    }
+                }
+                float pA = 0.0f, pB = 0.0f;
+#pragma unroll
+                for (int t = 0; t < 16; ++t) {
+                    pA = fmaf(R1[t], DA[t], pA);
+                    pB = fmaf(R2[t], DB[t], pB);
+                }
+                swap_halves(pA, pB);
+                acc += pA + pB;
+            }
+        }
+    }
+};
+
+template <int NEXT>
+__device__ __forceinline__ void load_event(const double* __restrict__ p, int64_t n, int64_t e, double (&pe)[NEXT][4])
+{
+#pragma unroll
+    for (int l = 0; l < NEXT; ++l)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) pe[l][c] = p[(l * 4 + c) * n + e];
+}
+
+// All 64 lanes of a wave take part in every MFMA, so lanes past the end of
+// the batch recompute the last event and do not store.
+template <int PROC, int MODE>
+__global__ __launch_bounds__(256) void k_me_mfma(const double* __restrict__ p, int64_t n, float* __restrict__ out,
+                                                 double mt, double coupling)
+{
+    const int64_t e0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t e = e0 < n ? e0 : n - 1;
+    if constexpr (PROC == GG_TT) {
+        double pe[4][4];
+        load_event<4>(p, n, e, pe);
+        MfmaColour<2, MODE> sink;
+        sink.init(me_gg_tt_cnum);
+        me_gg_tt_amps<float>(pe, mt, sink);
+        if (e0 < n) out[e0] = (float)((double)sink.acc * coupling * me_gg_tt_norm_noalpha());
+    } else if constexpr (PROC == GG_TTG) {
+        double pe[5][4];
+        load_event<5>(p, n, e, pe);
+        MfmaColour<6, MODE> sink;
+        sink.init(me_gg_ttg_cnum);
+        me_gg_ttg_amps<float>(pe, mt, sink);
+        if (e0 < n) out[e0] = (float)((double)sink.acc * coupling * me_gg_ttg_norm_noalpha());
+    } else {
+        double pe[6][4];
+        load_event<6>(p, n, e, pe);
+        MfmaColour<24, MODE> sink;
+        sink.init(me_gg_ttgg_cnum);
+        me_gg_ttgg_amps<float>(pe, mt, sink);
+        if (e0 < n) out[e0] = (float)((double)sink.acc * coupling * me_gg_ttgg_norm_noalpha());
+    }
+}
+
+template <int MODE>
+hipError_t launch_mode(const MeJob& j, double mt, double coupling, int block, hipStream_t s)
+{
+    const unsigned grid = (unsigned)((j.n + block - 1) / block);
+    float* out = static_cast<float*>(j.out);
+    switch (j.proc) {
+    case GG_TT: hipLaunchKernelGGL((k_me_mfma<GG_TT, MODE>), dim3(grid), dim3(block), 0, s, j.p, j.n, out, mt, coupling); break;
+    case GG_TTG: hipLaunchKernelGGL((k_me_mfma<GG_TTG, MODE>), dim3(grid), dim3(block), 0, s, j.p, j.n, out, mt, coupling); break;
+    case GG_TTGG: hipLaunchKernelGGL((k_me_mfma<GG_TTGG, MODE>), dim3(grid), dim3(block), 0, s, j.p, j.n, out, mt, coupling); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_matrix_element_mfma(const MeJob& j, int precision, double mt, double coupling, int block,
+                                      hipStream_t s)
+{
+    if (block <= 0 || block % 64) block = 256;
+    if (precision == 3) return launch_mode<0>(j, mt, coupling, block, s);
+    if (precision == 2) return launch_mode<1>(j, mt, coupling, block, s);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace mf

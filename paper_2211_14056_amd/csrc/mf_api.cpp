@@ -83,6 +83,8 @@ const char* mf_last_error(void) { return g_err.c_str(); }
 int mf_process_legs(int proc) { return valid_proc(proc) ? mf::n_ext(proc) : -1; }
 int mf_process_dims(int proc) { return valid_proc(proc) ? mf::dims(proc) : -1; }
 
+int mf_precision_available(int precision) { return mf::precision_available(precision) ? 1 : 0; }
+
 mf_status mf_create(int device, mf_handle* out)
 {
     g_err.clear();
@@ -230,16 +232,44 @@ mf_status mf_matrix_element_vjp(mf_handle h, const mf_request* reqs, int n_reqs,
     if (!h) return fail(MF_ERR_INVALID_ARG, "mf_matrix_element_vjp: NULL handle");
     mf_status st = check_requests("mf_matrix_element_vjp", reqs, n_reqs, precision, prm, true);
     if (st != MF_OK) return st;
-    (void)edges;
-    (void)nb;
-    (void)stream;
-    return fail(MF_ERR_UNSUPPORTED, "mf_matrix_element_vjp: not available in this build");
+    if (edges && (nb < 2 || nb > 64))
+        return fail(MF_ERR_INVALID_ARG, "mf_matrix_element_vjp: nb = %d outside [2, 64]", nb);
+    for (int i = 0; i < n_reqs; ++i)
+        if (reqs[i].proc == MF_EE_MUMU && reqs[i].n > 0)
+            return fail(MF_ERR_UNSUPPORTED, "mf_matrix_element_vjp: no derivative for MF_EE_MUMU");
+    if (!(2.0 * prm->m_t < prm->sqrt_s && prm->m_t >= 0.0 && prm->alpha_s > 0.0))
+        return fail(MF_ERR_INVALID_ARG, "mf_matrix_element_vjp: need 0 <= 2 m_t < sqrt_s and alpha_s > 0");
+    DeviceGuard g(h->device);
+    for (int i = 0; i < n_reqs; ++i) {
+        const mf_request& r = reqs[i];
+        if (r.n == 0) continue;
+        mf::VjpJob j{};
+        j.proc = r.proc;
+        j.n = r.n;
+        j.x = r.x;
+        j.grad_me = r.grad_me;
+        j.grad_x = r.grad_x;
+        j.grad_theta = r.grad_theta;
+        j.me_out = r.me_out;
+        j.me_f32 = precision != MF_FP64;
+        j.edges = edges;
+        j.nb = nb;
+        j.sqrt_s = prm->sqrt_s;
+        j.mt = prm->m_t;
+        j.alpha_s = prm->alpha_s;
+        double coupling = 1.0;
+        for (int k = 0; k < mf::n_gluons(r.proc); ++k) coupling *= 4.0 * 3.141592653589793238463 * prm->alpha_s;
+        j.coupling = coupling;
+        hipError_t e = mf::launch_vjp(j, precision == MF_FP64 ? 0 : 1, static_cast<hipStream_t>(stream));
+        if (e != hipSuccess) return hip_fail(e, "mf_matrix_element_vjp launch");
+    }
+    return MF_OK;
 }
 
 mf_status mf_vegas_refine(mf_handle h, const mf_params* prm, int64_t n, int d, int nb, double alpha,
                           const double* w, const double* jac, const void* me, int me_f32,
                           const uint8_t* pass, const int16_t* bin_idx, double* F, double* acc,
-                          double* edges, int update_edges, uint64_t* rng_counter, void* stream)
+                          double* edges, int flags, uint64_t* rng_counter, void* stream)
 {
     g_err.clear();
     if (!h) return fail(MF_ERR_INVALID_ARG, "mf_vegas_refine: NULL handle");
@@ -271,7 +301,8 @@ mf_status mf_vegas_refine(mf_handle h, const mf_params* prm, int64_t n, int d, i
     a.partials = h->partials;
     a.acc = acc;
     a.edges = edges;
-    a.update_edges = update_edges;
+    a.update_edges = (flags & MF_VEGAS_REFINE) ? 1 : 0;
+    a.accumulate = (flags & MF_VEGAS_ACCUMULATE) ? 1 : 0;
     a.rng_counter = rng_counter;
     hipError_t e = mf::launch_vegas(a, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "mf_vegas_refine launch");

@@ -15,45 +15,10 @@
 #include "internal.h"
 #include "rng.h"
 
+#include "ps_core.h"
+
 namespace mf {
 namespace {
-
-constexpr double kTwoPi = 6.283185307179586476925;
-
-__device__ __forceinline__ void boost_from_rest(const double p[4], const double Q[4], double M, double out[4])
-{
-    // p given in the rest frame of Q (invariant mass M, known from the
-    // recursion rather than recomputed from Q, which would cancel for a
-    // strongly boosted light system) -> frame where Q has momentum Q
-    const double qp = Q[1] * p[1] + Q[2] * p[2] + Q[3] * p[3];
-    const double E = (Q[0] * p[0] + qp) / M;
-    const double fac = (p[0] + E) / (Q[0] + M);
-    out[0] = E;
-    out[1] = p[1] + Q[1] * fac;
-    out[2] = p[2] + Q[2] * fac;
-    out[3] = p[3] + Q[3] * fac;
-}
-
-// Solve u = (a+1) rho^a - a rho^(a+1) for rho = r^2 in [0,1] (increasing):
-// safeguarded Newton inside a shrinking bracket.
-__device__ double solve_mass_ratio(double u, int a)
-{
-    double lo = 0.0, hi = 1.0;
-    double rho = (a == 1) ? 1.0 - sqrt(1.0 - u) : pow(u / (a + 1), 1.0 / a);
-    if (!(rho > 0.0 && rho < 1.0)) rho = 0.5;
-    for (int it = 0; it < 100; ++it) {
-        const double ra = pow(rho, a - 1);
-        const double f = ((a + 1) - a * rho) * ra * rho - u;
-        if (f == 0.0) break;                       // exact root
-        if (f > 0.0) hi = rho; else lo = rho;
-        const double df = a * (a + 1) * ra * (1.0 - rho);
-        double nr = rho - f / df;
-        if (!(nr >= lo && nr <= hi)) nr = 0.5 * (lo + hi);
-        if (fabs(nr - rho) <= 2.5e-16 * rho || hi - lo <= 2.5e-16 * hi) { rho = nr; break; }
-        rho = nr;
-    }
-    return sqrt(rho);
-}
 
 template <int NOUT>
 __global__ __launch_bounds__(256) void k_phase_space(PsArgs a)
@@ -101,93 +66,12 @@ __global__ __launch_bounds__(256) void k_phase_space(PsArgs a)
             }
         }
     }
-    // ---- a3: massless momenta (RAMBO on diet)
+    // ---- a3: RAMBO on diet + massive rescaling
     const double rs = a.sqrt_s;
-    double M[NOUT];
-    M[0] = rs;
-#pragma unroll
-    for (int i = 2; i < NOUT; ++i) M[i - 1] = solve_mass_ratio(y[i - 2], NOUT - i) * M[i - 2];
-    M[NOUT - 1] = 0.0;
     double P[NOUT][4];
-    double Q[4] = {rs, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int i = 1; i < NOUT; ++i) {
-        const double Mi = M[i - 1], Mn = M[i];
-        const double q = (Mi * Mi - Mn * Mn) / (2.0 * Mi);
-        const double cth = 2.0 * y[(NOUT - 2) + 2 * (i - 1)] - 1.0;
-        const double ph = kTwoPi * y[(NOUT - 2) + 2 * (i - 1) + 1];
-        const double sth = sqrt(fmax(1.0 - cth * cth, 0.0));
-        double sph, cph;
-        sincos(ph, &sph, &cph);
-        const double nv[3] = {sth * cph, sth * sph, cth};
-        const double pr[4] = {q, q * nv[0], q * nv[1], q * nv[2]};
-        const double Qr[4] = {sqrt(q * q + Mn * Mn), -q * nv[0], -q * nv[1], -q * nv[2]};
-        double Qn[4];
-        boost_from_rest(pr, Q, Mi, P[i - 1]);
-        boost_from_rest(Qr, Q, Mi, Qn);
-#pragma unroll
-        for (int c = 0; c < 4; ++c) Q[c] = Qn[c];
-    }
-#pragma unroll
-    for (int c = 0; c < 4; ++c) P[NOUT - 1][c] = Q[c];
-    // massless volume (2pi)^(4-3n) (pi/2)^(n-1) s^(n-2) / ((n-1)! (n-2)!)
-    double wgt = 1.0;
-    {
-        const double s = rs * rs;
-        double v = 1.0;
-        for (int i = 0; i < 3 * NOUT - 4; ++i) v /= kTwoPi;
-        for (int i = 0; i < NOUT - 1; ++i) v *= 0.5 * 3.141592653589793238463;
-        for (int i = 0; i < NOUT - 2; ++i) v *= s;
-        double f = 1.0;
-        for (int i = 2; i <= NOUT - 1; ++i) f *= i;
-        for (int i = 2; i <= NOUT - 2; ++i) f *= i;
-        wgt = v / f;
-    }
-    // ---- massive rescaling: sum sqrt(m^2 + xi^2 E^2) = sqrt(s)
-    double msum = 0.0;
-#pragma unroll
-    for (int i = 0; i < NOUT; ++i) msum += a.m_out[i];
-    if (msum > 0.0) {
-        double lo = 0.0, hi = 1.0;
-        double xi = sqrt(fmax(1.0 - (msum / rs) * (msum / rs), 0.0));
-        bool ok = false;
-        for (int it = 0; it < 50; ++it) {
-            double F = -rs, dF = 0.0;
-#pragma unroll
-            for (int i = 0; i < NOUT; ++i) {
-                const double E = P[i][0];
-                const double r = sqrt(a.m_out[i] * a.m_out[i] + xi * xi * E * E);
-                F += r;
-                dF += xi * E * E / r;
-            }
-            if (F == 0.0) { ok = true; break; }     // exact root
-            if (F > 0.0) hi = xi; else lo = xi;
-            double nx = xi - F / dF;
-            if (!(nx >= lo && nx <= hi)) nx = 0.5 * (lo + hi);
-            const double dx = fabs(nx - xi);
-            xi = nx;
-            if (dx <= 1e-15 * xi) { ok = true; break; }
-        }
-        if (!ok) {
-            wgt = 0.0;
-            if (a.fail_count) atomicAdd(a.fail_count, 1ull);
-        }
-        double sk = 0.0, pk = 1.0, s2 = 0.0;
-#pragma unroll
-        for (int i = 0; i < NOUT; ++i) {
-            const double E = P[i][0];
-            const double k0 = sqrt(a.m_out[i] * a.m_out[i] + xi * xi * E * E);
-            P[i][0] = k0;
-            P[i][1] *= xi; P[i][2] *= xi; P[i][3] *= xi;
-            const double ka = sqrt(P[i][1] * P[i][1] + P[i][2] * P[i][2] + P[i][3] * P[i][3]);
-            sk += ka;
-            pk *= ka / k0;
-            s2 += ka * ka / k0;
-        }
-        double fac = 1.0;
-        for (int i = 0; i < 2 * NOUT - 3; ++i) fac *= sk / rs;
-        wgt *= fac * pk * rs / s2;
-    }
+    double wgt = 0.0;
+    const bool ok = rambo_event<NOUT, double>(y, rs, a.m_out, P, &wgt);
+    if (!ok && a.fail_count) atomicAdd(a.fail_count, 1ull);
     // ---- a4: cuts on the final gluons (outgoing index >= 2 for the gg processes)
     bool pass = true;
     if (a.pass) {
@@ -207,7 +91,7 @@ __global__ __launch_bounds__(256) void k_phase_space(PsArgs a)
             double dphi = phi_[0] - phi_[1];
             // wrap into [-pi, pi): same convention as remainder(x + pi, 2 pi) - pi
             dphi = dphi + 3.141592653589793238463;
-            dphi = dphi - kTwoPi * floor(dphi / kTwoPi);
+            dphi = dphi - kTwoPiPs * floor(dphi / kTwoPiPs);
             dphi = dphi - 3.141592653589793238463;
             const double deta = eta_[0] - eta_[1];
             pass = pass && (sqrt(deta * deta + dphi * dphi) > a.dr_min);

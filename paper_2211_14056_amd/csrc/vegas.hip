@@ -132,7 +132,7 @@ __global__ __launch_bounds__(VB) void k_vegas_finalize(VegasArgs a)
     for (int c = threadIdx.x; c < stride; c += VB) {
         double s = 0.0;
         for (int b = 0; b < a.nblk; ++b) s += a.partials[(int64_t)b * stride + c];
-        a.acc[c] = s;
+        a.acc[c] = a.accumulate ? a.acc[c] + s : s;
     }
     __syncthreads();
     if (a.update_edges && threadIdx.x < a.d) {

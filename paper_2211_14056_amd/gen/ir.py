@@ -83,6 +83,8 @@ class Block:
             return b
         if b.is_const and b.val == 0.0:
             return a
+        if not a.is_const and not b.is_const and (b.name == f'(-{a.name})' or a.name == f'(-{b.name})'):
+            return ZERO                          # x + (-x)
         return self.new(f'{self.ref(a)} + {self.ref(b)}', 1)
 
     def sub(self, a, b):

@@ -125,46 +125,47 @@ def emit_qcd(proc, with_colour=True):
     fn = f'me_{proc.name}'
     out.append(f'// ---- {proc.name}: {k} gluons, {math.factorial(k)} colour orderings, '
                f'{2 ** (k + 2)} helicities')
-    out.append(f'template <typename R, typename Sink>')
-    out.append(f'__device__ __forceinline__ void {fn}_body(const double (&p)[{proc.n_ext}][4], '
-               f'const double mt, Sink& sink)')
+    out.append(f'template <typename R, typename KT, typename Sink>')
+    out.append(f'__device__ __forceinline__ void {fn}_body(const KT (&p)[{proc.n_ext}][4], '
+               f'const KT mt, Sink& sink)')
     out.append('{')
     # ---------------- prologue (double precision kinematics) ----------------
     pro = []
     # incoming-convention momenta k_i of the gluons
     for gi, leg in enumerate(proc.gl_legs):
         sgn = '' if leg < 2 else '-'
-        pro.append(f'const double k{gi}[4] = {{{sgn}p[{leg}][0], {sgn}p[{leg}][1], '
+        pro.append(f'const KT k{gi}[4] = {{{sgn}p[{leg}][0], {sgn}p[{leg}][1], '
                    f'{sgn}p[{leg}][2], {sgn}p[{leg}][3]}};')
-    pro.append('const double mt2 = mt * mt;')
+    pro.append('const KT mt2 = mt * mt;')
     # gluon propagators 1/P_S^2
     for sub in proc.gluon_subsets():
         n = _sname(sub)
         terms = ' + '.join(f'k{i}[c]' for i in sub)
-        pro.append(f'double P{n}[4]; for (int c = 0; c < 4; ++c) P{n}[c] = {terms};')
-        pro.append(f'const R ig{n} = R(1.0 / (P{n}[0] * P{n}[0] - P{n}[1] * P{n}[1] - '
+        pro.append(f'KT P{n}[4]; for (int c = 0; c < 4; ++c) P{n}[c] = {terms};')
+        pro.append(f'const R ig{n} = cvt<R>(KT(1.0) / (P{n}[0] * P{n}[0] - P{n}[1] * P{n}[1] - '
                    f'P{n}[2] * P{n}[2] - P{n}[3] * P{n}[3]));')
     # quark propagators: q = p_t - P_S, 1/(q^2 - m^2)
     for sub in proc.quark_subsets():
         n = _sname(sub)
         terms = ' - '.join([f'p[2][c]'] + [f'k{i}[c]' for i in sub])
-        pro.append(f'double q{n}[4]; for (int c = 0; c < 4; ++c) q{n}[c] = {terms};')
-        pro.append(f'const R iq{n} = R(1.0 / ((q{n}[0] - q{n}[3]) * (q{n}[0] + q{n}[3]) - '
+        pro.append(f'KT q{n}[4]; for (int c = 0; c < 4; ++c) q{n}[c] = {terms};')
+        pro.append(f'const R iq{n} = cvt<R>(KT(1.0) / ((q{n}[0] - q{n}[3]) * (q{n}[0] + q{n}[3]) - '
                    f'q{n}[1] * q{n}[1] - q{n}[2] * q{n}[2] - mt2));')
     # momenta in working precision
     for gi in range(k):
-        pro.append(f'const R K{gi}[4] = {{R(k{gi}[0]), R(k{gi}[1]), R(k{gi}[2]), R(k{gi}[3])}};')
-    pro.append('const R PT[4] = {R(p[2][0]), R(p[2][1]), R(p[2][2]), R(p[2][3])};')
-    pro.append('const R MT = R(mt);')
+        pro.append(f'const R K{gi}[4] = {{cvt<R>(k{gi}[0]), cvt<R>(k{gi}[1]), cvt<R>(k{gi}[2]), '
+                   f'cvt<R>(k{gi}[3])}};')
+    pro.append('const R PT[4] = {cvt<R>(p[2][0]), cvt<R>(p[2][1]), cvt<R>(p[2][2]), cvt<R>(p[2][3])};')
+    pro.append('const R MT = cvt<R>(mt);')
     # outgoing-gluon polarisation bases (eps1/sqrt2, eps2/sqrt2)
     for gi, leg in enumerate(proc.gl_legs):
         if leg < 2:
             continue
-        pro.append(f'R e{gi}u[3], e{gi}w[2]; pol_basis<R>(p[{leg}], e{gi}u, e{gi}w);')
+        pro.append(f'R e{gi}u[3], e{gi}w[2]; pol_basis<R, KT>(p[{leg}], e{gi}u, e{gi}w);')
     # spinors for both helicities
     pro.append('cplx<R> ub[2][4], vs[2][4];')
-    pro.append('ubar_spinor<R>(p[2], mt, -1, ub[0]); ubar_spinor<R>(p[2], mt, 1, ub[1]);')
-    pro.append('v_spinor<R>(p[3], mt, -1, vs[0]); v_spinor<R>(p[3], mt, 1, vs[1]);')
+    pro.append('ubar_spinor<R, KT>(p[2], mt, -1, ub[0]); ubar_spinor<R, KT>(p[2], mt, 1, ub[1]);')
+    pro.append('v_spinor<R, KT>(p[3], mt, -1, vs[0]); v_spinor<R, KT>(p[3], mt, 1, vs[1]);')
     out += ['    ' + l for l in pro]
 
     # ---------------- loop body (working precision) ----------------
@@ -389,14 +390,12 @@ def emit_qcd(proc, with_colour=True):
         body += ['        ' + l for l in cs.lines]
         body.append(f'        sink.add({cs.ref(csq[0])}, {cs.ref(csq[1])});')
     else:
-        # expose the amplitudes to the sink (colour contraction done elsewhere)
-        body.append(f'        sink.amplitudes(')
+        # hand the partial amplitudes to the sink (colour contraction done there)
         for h in range(2):
             for si in range(n_or):
                 a = amps[h][si]
-                sep = ',' if (h, si) != (1, n_or - 1) else ''
-                body.append(f'            {q.ref(a.re)}, {q.ref(a.im)}{sep}')
-        body.append('        );')
+                body.append(f'        sink.a[{h}][{si}][0] = {q.ref(a.re)}; sink.a[{h}][{si}][1] = {q.ref(a.im)};')
+        body.append('        sink.flush();')
     body.append('    }')
     body.append('}')
     out += ['    ' + l for l in body]
@@ -432,7 +431,7 @@ def emit_all(outdir):
         src_a = src_a.replace(f'me_{name}_body', f'me_{name}_amps')
         cnum, cden = proc.cnum, proc.cden
         ctab = [f'// colour matrix numerators for {name} (denominator {cden})',
-                f'__device__ __constant__ const signed short me_{name}_cnum[{len(cnum)}][{len(cnum)}] = {{']
+                f'static __constant__ const short me_{name}_cnum[{len(cnum)}][{len(cnum)}] = {{']
         for row in cnum:
             ctab.append('    {' + ', '.join(str(v) for v in row) + '},')
         ctab.append('};')

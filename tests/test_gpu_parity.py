@@ -160,6 +160,29 @@ def test_me_fp32_vs_oracle(h, proc):
     assert np.median(rel) < 1e-5 and rel.max() < 1e-3
 
 
+@pytest.mark.parametrize('prec', ['fp32_mfma_f32', 'fp32_mfma_bf16'])
+@pytest.mark.parametrize('proc', ['gg_tt', 'gg_ttg', 'gg_ttgg'])
+def test_me_mfma_colour_vs_oracle(h, proc, prec):
+    n = ME_N[proc] + 5          # not a multiple of the wave size: tail lanes recompute, do not store
+    say('me', prec, proc, n)
+    ev = gpu_events(h, proc, n, seed=23)
+    me = gpu_me(h, proc, ev['p'], mf.PRECISION[prec])
+    ref = oracle_me(proc, ev['p'].cpu().numpy())
+    ok = ev['pass_'].cpu().numpy().astype(bool)
+    rel = np.abs(me / ref - 1)[ok]
+    say('  median', np.median(rel), 'max', rel.max())
+    assert np.median(rel) < 1e-5 and rel.max() < 1e-3
+
+
+@pytest.mark.parametrize('n', [1, 63, 65, 257])
+def test_me_mfma_ragged_batches(h, n):
+    say('mfma ragged', n)
+    ev = gpu_events(h, 'gg_ttgg', n, seed=24)
+    a = gpu_me(h, 'gg_ttgg', ev['p'], mf.MF_FP32_MFMA_F32)
+    b = gpu_me(h, 'gg_ttgg', ev['p'], mf.MF_FP64)
+    assert np.abs(a / b - 1).max() < 1e-3
+
+
 def test_me_closed_forms_on_gpu(h):
     # e+e- -> mu+mu- and gg -> ttbar against their closed forms, per event
     for proc in ('ee_mumu', 'gg_tt'):
@@ -322,3 +345,132 @@ def test_vegas_gg_tt_closed_form(h):
     ref = closed_forms.gg_tt_sigma(P['sqrt_s'] ** 2, P['m_t'], P['alpha_s']) * closed_forms.GEV2_TO_PB
     say('  sigma', I, '+-', sig, 'closed form', ref)
     assert abs(I - ref) < 3 * sig
+
+
+# ------------------------------------------------------------------ a9: derivative
+def _vjp_gpu(h, proc, x, gbar, precision, edges=None):
+    pid = mf.PROCESS[proc]
+    d, n = x.shape
+    dev = torch.device('cuda', 0)
+    xt = torch.tensor(x, dtype=torch.float64, device=dev).contiguous()
+    gb = torch.tensor(gbar, dtype=torch.float64, device=dev).contiguous()
+    gx = torch.empty(d, n, dtype=torch.float64, device=dev)
+    gth = torch.empty(n, 2, dtype=torch.float64, device=dev)
+    me = torch.empty(n, dtype=torch.float64 if precision == mf.MF_FP64 else torch.float32, device=dev)
+    e = None if edges is None else torch.tensor(edges, dtype=torch.float64, device=dev).contiguous()
+    req = mf.make_request(pid, None, me, x=xt, grad_me=gb, grad_x=gx, grad_theta=gth, n=n)
+    mf.mf_matrix_element_vjp(h, [req], precision, prm_of(proc), edges=e, nb=50)
+    torch.cuda.synchronize()
+    return me.double().cpu().numpy(), gx.cpu().numpy(), gth.cpu().numpy()
+
+
+def _edges(d, seed):
+    rng = np.random.default_rng(seed)
+    w_ = rng.uniform(0.5, 1.5, (d, 50))
+    e = np.concatenate([np.zeros((d, 1)), np.cumsum(w_, 1) / w_.sum(1, keepdims=True)], 1)
+    e[:, -1] = 1.0
+    return e
+
+
+def _normwise(a, b):
+    """Per event: max_k |a_k - b_k| / max_k |b_k| over the derivative components."""
+    return np.abs(a - b).max(0) / np.abs(b).max(0)
+
+
+VJP_N = {'gg_tt': 64, 'gg_ttg': 24, 'gg_ttgg': 4}
+
+
+@pytest.mark.parametrize('proc', ['gg_tt', 'gg_ttg', 'gg_ttgg'])
+def test_vjp_fp64_vs_oracle_reverse_mode(h, proc):
+    from oracle import grad as ograd
+    n = VJP_N[proc]
+    d = processes.dims(proc)
+    x = philox.uniforms(41, n, d)
+    edges = _edges(d, 3)
+    gbar = np.random.default_rng(1).uniform(0.5, 2.0, n)
+    say('vjp fp64', proc, n)
+    me, gx, gth = _vjp_gpu(h, proc, x, gbar, mf.MF_FP64, edges)
+    me_o, gx_o, gth_o = ograd.vjp(proc, P, x, gbar, edges)
+    assert np.abs(me / me_o - 1).max() < 1e-12
+    ga = np.concatenate([gx, gth[:, :1].T], 0)
+    gb = np.concatenate([gx_o, gth_o[:, :1].T], 0)
+    err = _normwise(ga, gb)
+    say('  max normwise', err.max())
+    assert err.max() < 1e-10
+    assert np.abs(gth[:, 1] / gth_o[:, 1] - 1).max() < 1e-12
+
+
+@pytest.mark.parametrize('proc', ['gg_tt', 'gg_ttg'])
+def test_vjp_fp32_vs_oracle(h, proc):
+    from oracle import grad as ograd
+    n = VJP_N[proc]
+    d = processes.dims(proc)
+    x = philox.uniforms(42, n, d)
+    gbar = np.ones(n)
+    say('vjp fp32', proc, n)
+    me, gx, gth = _vjp_gpu(h, proc, x, gbar, mf.MF_FP32)
+    me_o, gx_o, gth_o = ograd.vjp(proc, P, x, gbar)
+    ga = np.concatenate([gx, gth[:, :1].T], 0)
+    gb = np.concatenate([gx_o, gth_o[:, :1].T], 0)
+    err = _normwise(ga, gb)
+    say('  median', np.median(err), 'max', err.max())
+    assert np.median(err) < 1e-4 and err.max() < 1e-2
+
+
+def test_vjp_vs_finite_differences_ttg(h):
+    """Central differences (h = 1e-6) of the FP64 oracle, the configuration of the tt g derivative run."""
+    from oracle import grad as ograd
+    proc, n = 'gg_ttg', 8
+    d = processes.dims(proc)
+    x = 0.05 + 0.9 * philox.uniforms(43, n, d)
+    say('vjp vs FD', proc, n)
+    me, gx, gth = _vjp_gpu(h, proc, x, np.ones(n), mf.MF_FP64)
+    fx, fm = ograd.finite_difference(proc, P, x)
+    ga = np.concatenate([gx, gth[:, :1].T], 0)
+    gb = np.concatenate([fx, fm[None, :]], 0)
+    assert _normwise(ga, gb).max() < 1e-6
+
+
+def test_vjp_full_size_ttg_sampled(h):
+    """4e6 events (the tt g derivative configuration): finite, forward value equal to mf_matrix_element."""
+    proc, n = 'gg_ttg', 4_000_000
+    pid = mf.PROCESS[proc]
+    d = processes.dims(proc)
+    say('vjp full size', proc, n)
+    ev = gpu_events(h, proc, n, seed=44)
+    dev = torch.device('cuda', 0)
+    gx = torch.empty(d, n, dtype=torch.float64, device=dev)
+    gth = torch.empty(n, 2, dtype=torch.float64, device=dev)
+    gb = torch.ones(n, dtype=torch.float64, device=dev)
+    me = torch.empty(n, dtype=torch.float32, device=dev)
+    req = mf.make_request(pid, None, me, x=ev['x'], grad_me=gb, grad_x=gx, grad_theta=gth, n=n)
+    mf.mf_matrix_element_vjp(h, [req], mf.MF_FP32, prm_of(proc))
+    me_fwd = mf.matrix_element(h, pid, ev['p'], mf.MF_FP32)
+    torch.cuda.synchronize()
+    assert bool(torch.isfinite(gx).all()) and bool(torch.isfinite(gth).all())
+    assert float(((me.double() - me_fwd.double()).abs() / me_fwd.double()).max()) < 1e-5
+    from oracle import grad as ograd
+    idx = np.random.default_rng(2).choice(n, 6, replace=False)
+    x = ev['x'][:, idx].cpu().numpy()
+    me_o, gx_o, gth_o = ograd.vjp(proc, P, x, np.ones(6))
+    ga = np.concatenate([gx[:, idx].cpu().numpy(), gth[idx, :1].cpu().numpy().T], 0)
+    gbb = np.concatenate([gx_o, gth_o[:, :1].T], 0)
+    assert _normwise(ga, gbb).max() < 1e-2
+
+
+def test_autograd_function(h):
+    from oracle import grad as ograd
+    from paper_2211_14056_amd.autograd import MatrixElementFn
+    proc, n = 'gg_ttg', 16
+    d = processes.dims(proc)
+    x0 = philox.uniforms(45, n, d)
+    x = torch.tensor(x0, dtype=torch.float64, device='cuda', requires_grad=True)
+    theta = torch.tensor([P['m_t'], P['alpha_s']], dtype=torch.float64, requires_grad=True)
+    say('autograd', proc, n)
+    me = MatrixElementFn.apply(x, theta, h, proc, mf.MF_FP64, None, mf.params_from_dict(P))
+    (2.0 * me).sum().backward()
+    me_o, gx_o, gth_o = ograd.vjp(proc, P, x0, 2.0 * np.ones(n))
+    assert np.abs(me.detach().cpu().numpy() / me_o - 1).max() < 1e-12
+    assert _normwise(x.grad.cpu().numpy(), gx_o).max() < 1e-10
+    assert abs(theta.grad[0].item() / gth_o[:, 0].sum() - 1) < 1e-10
+    assert abs(theta.grad[1].item() / gth_o[:, 1].sum() - 1) < 1e-12
