@@ -9,7 +9,7 @@ path is measured on the same batches and reported beside it, with the
 per-event relative difference of the FP32 result from the FP64 one (the FP64
 path matches the FP64 CPU oracle to 1e-12 in the parity tests).
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp32_mfma_bf16]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp32_mfma_f32]
 """
 import argparse
 import json
@@ -30,6 +30,7 @@ PROC = 'gg_ttgg'
 BATCH = 1_000_000
 BATCHES_PER_ITER = 16
 NB = 50
+COPY_BYTES = 512 << 20
 
 
 def flops_per_event(proc):
@@ -57,36 +58,31 @@ def run_path(mf, h, prm, precision, steps, warmup, seed):
     edges = torch.tensor(np.tile(np.linspace(0, 1, NB + 1), (d, 1)), **f64).contiguous()
     acc = torch.zeros(2 + d * NB, **f64)
     req = [mf.make_request(pid, p, me)]
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    me_ms = []
+    # HIP events around every matrix-element launch of the timed region, recorded on
+    # the stream the library launches on (torch's current stream); read after the end
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
 
-    def step(i, timed):
+    def step(i, ev=None):
         mf.mf_phase_space(h, pid, prm, BATCH, seed=seed, offset=i * BATCH, edges=edges, nb=NB, p=p, w=w,
                           pass_=pas, bin_idx=bins, jac=jac)
-        if timed:
-            ev0.record()
+        if ev:
+            ev[0].record()
         mf.mf_matrix_element(h, req, precision, prm)
-        if timed:
-            ev1.record()
+        if ev:
+            ev[1].record()
         last = (i + 1) % BATCHES_PER_ITER == 0
         mf.mf_vegas_refine(h, prm, BATCH, d, NB, 1.5, w, jac, me, pas, bins, acc, edges,
                            update_edges=last, accumulate=(i % BATCHES_PER_ITER) != 0)
-        if timed:
-            ev1.synchronize()
-            me_ms.append(ev0.elapsed_time(ev1))
 
     for i in range(warmup):
-        step(i, False)
-    torch.cuda.synchronize()
-    # ME kernel alone, event-timed on the launch stream (not part of the whole-path clock)
-    for i in range(min(steps, 5)):
-        step(warmup + i, True)
+        step(i)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(steps):
-        step(warmup + i, False)
+        step(warmup + i, evs[i])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    me_ms = [a.elapsed_time(b) for a, b in evs]
     return dict(seconds=t1 - t0, me_ms=float(np.mean(me_ms)), me=me, pas=pas, acc=acc)
 
 
@@ -123,6 +119,8 @@ def main():
     ap.add_argument('--precision', default='auto')
     ap.add_argument('--no-cpu-baseline', action='store_true')
     ap.add_argument('--seed', type=int, default=4)
+    ap.add_argument('--copy-calibration', action='store_true',
+                    help=f'also run one {COPY_BYTES >> 20} MiB device-to-device copy (counter calibration)')
     args = ap.parse_args()
     if args.gpus != 1:
         print(f'bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); '
@@ -133,8 +131,15 @@ def main():
     torch.cuda.init()
     h = mf.Handle(0)
     prm = mf.params()
+    if args.copy_calibration:
+        # a plain device copy of known size, so that HBM byte counters read for
+        # the kernels of this run can be scaled by what they read for it
+        src = torch.empty(COPY_BYTES // 8, dtype=torch.float64, device='cuda').fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
     if args.precision == 'auto':
-        prec = mf.MF_FP32_MFMA_BF16 if mf.has_precision(mf.MF_FP32_MFMA_BF16) else mf.MF_FP32
+        prec = mf.MF_FP32_MFMA_F32
     else:
         prec = mf.PRECISION[args.precision]
     head = run_path(mf, h, prm, prec, args.steps, args.warmup, args.seed)

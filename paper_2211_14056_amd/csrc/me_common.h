@@ -138,6 +138,13 @@ __device__ __forceinline__ void pol_basis(const KT* k, R u[3], R w[2])
     w[1] = cvt<R>(r * cph);
 }
 
+// Declares a value as changed by an empty asm statement: values derived from
+// it cannot be hoisted out of the enclosing loop, so they are recomputed
+// there instead of occupying registers across the loop.  No instruction.
+__device__ __forceinline__ void opaque(float& x) { asm volatile("" : "+v"(x)); }
+__device__ __forceinline__ void opaque(double& x) { asm volatile("" : "+v"(x)); }
+template <typename T> __device__ __forceinline__ void opaque(Dual<T>& x) { opaque(x.v); opaque(x.t); }
+
 // Helicity-sum accumulator used by the VALU colour path.
 template <typename R>
 struct HelicitySum {

@@ -109,13 +109,28 @@ __global__ __launch_bounds__(256) void k_me_valu(const double* __restrict__ p, i
         HelicitySum<R> hs;
         me_gg_ttg_body<R>(pe, mt, hs);
         out[e] = R((double)hs.acc * coupling * me_gg_ttg_norm_noalpha());
-    } else {
-        double pe[6][4];
-        load_event<6>(p, n, e, pe);
-        HelicitySum<R> hs;
-        me_gg_ttgg_body<R>(pe, mt, hs);
-        out[e] = R((double)hs.acc * coupling * me_gg_ttgg_norm_noalpha());
     }
+}
+
+// gg -> ttbar gg: one wave per block; the multi-gluon currents are parked in
+// this wave's LDS columns (one per lane, stride 64) between the gluon-current
+// block and the quark line.
+template <typename R>
+__global__ __launch_bounds__(64) void k_me_ttgg(const double* __restrict__ p, int64_t n, R* __restrict__ out,
+                                                double mt, double coupling)
+{
+    constexpr int SLOTS = sizeof(R) == 4 ? me_gg_ttgg_lds32_slots : me_gg_ttgg_lds64_slots;
+    __shared__ R smem[SLOTS * 64];
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    double pe[6][4];
+    load_event<6>(p, n, e, pe);
+    HelicitySum<R> hs;
+    if constexpr (sizeof(R) == 4)
+        me_gg_ttgg_body_lds32<R>(pe, mt, hs, smem + threadIdx.x);
+    else
+        me_gg_ttgg_body_lds64<R>(pe, mt, hs, smem + threadIdx.x);
+    out[e] = R((double)hs.acc * coupling * me_gg_ttgg_norm_noalpha());
 }
 
 template <typename R>
@@ -127,7 +142,11 @@ hipError_t launch_valu(const MeJob& j, double mt, double coupling, int block, hi
     case EE_MUMU: hipLaunchKernelGGL((k_me_valu<EE_MUMU, R>), dim3(grid), dim3(block), 0, s, j.p, j.n, out, mt, coupling); break;
     case GG_TT: hipLaunchKernelGGL((k_me_valu<GG_TT, R>), dim3(grid), dim3(block), 0, s, j.p, j.n, out, mt, coupling); break;
     case GG_TTG: hipLaunchKernelGGL((k_me_valu<GG_TTG, R>), dim3(grid), dim3(block), 0, s, j.p, j.n, out, mt, coupling); break;
-    case GG_TTGG: hipLaunchKernelGGL((k_me_valu<GG_TTGG, R>), dim3(grid), dim3(block), 0, s, j.p, j.n, out, mt, coupling); break;
+    case GG_TTGG: {
+        const unsigned g64 = (unsigned)((j.n + 63) / 64);
+        hipLaunchKernelGGL((k_me_ttgg<R>), dim3(g64), dim3(64), 0, s, j.p, j.n, out, mt, coupling);
+        break;
+    }
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -165,11 +165,13 @@ __global__ __launch_bounds__(256) void k_me_mfma(const double* __restrict__ p, i
         me_gg_ttg_amps<float>(pe, mt, sink);
         if (e0 < n) out[e0] = (float)((double)sink.acc * coupling * me_gg_ttg_norm_noalpha());
     } else {
+        // one wave per block: multi-gluon currents parked in this wave's LDS columns
+        __shared__ float smem[me_gg_ttgg_amps_slots * 64];
         double pe[6][4];
         load_event<6>(p, n, e, pe);
         MfmaColour<24, MODE> sink;
         sink.init(me_gg_ttgg_cnum);
-        me_gg_ttgg_amps<float>(pe, mt, sink);
+        me_gg_ttgg_amps<float>(pe, mt, sink, smem + (threadIdx.x & 63));
         if (e0 < n) out[e0] = (float)((double)sink.acc * coupling * me_gg_ttgg_norm_noalpha());
     }
 }
@@ -182,7 +184,11 @@ hipError_t launch_mode(const MeJob& j, double mt, double coupling, int block, hi
     switch (j.proc) {
     case GG_TT: hipLaunchKernelGGL((k_me_mfma<GG_TT, MODE>), dim3(grid), dim3(block), 0, s, j.p, j.n, out, mt, coupling); break;
     case GG_TTG: hipLaunchKernelGGL((k_me_mfma<GG_TTG, MODE>), dim3(grid), dim3(block), 0, s, j.p, j.n, out, mt, coupling); break;
-    case GG_TTGG: hipLaunchKernelGGL((k_me_mfma<GG_TTGG, MODE>), dim3(grid), dim3(block), 0, s, j.p, j.n, out, mt, coupling); break;
+    case GG_TTGG: {
+        const unsigned g64 = (unsigned)((j.n + 63) / 64);
+        hipLaunchKernelGGL((k_me_mfma<GG_TTGG, MODE>), dim3(g64), dim3(64), 0, s, j.p, j.n, out, mt, coupling);
+        break;
+    }
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

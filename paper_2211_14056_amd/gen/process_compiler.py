@@ -118,16 +118,30 @@ def _sname(sub):
     return ''.join(str(i) for i in sub)
 
 
-def emit_qcd(proc, with_colour=True):
-    """Return (source text, flop counts) of the device function for ``proc``."""
+def emit_qcd(proc, with_colour=True, opaque_inputs=True, group_barriers=True, lds_budget=0, constants=True):
+    """Return (source text, flop counts) of the device function for ``proc``.
+
+    opaque_inputs: re-declare the momenta as opaque at the top of each helicity
+      iteration, so that their sums are recomputed inside the loop instead of
+      being hoisted and kept live across it (fewer registers, a few adds more).
+    group_barriers: scheduling barriers between the gluon-current block and the
+      quark line and between groups of orderings with the same first gluon, so
+      that the scheduler cannot interleave them and widen the live set.
+    lds_budget: number of working-type scalars per lane that may be parked in
+      LDS.  Multi-gluon currents (longest first) are written to per-lane LDS
+      slots when computed and re-read at each use on the quark line, so they do
+      not occupy registers across the top-helicity loop.  The emitted body then
+      takes an LDS pointer (this lane's column, stride 64) as extra argument.
+    """
     k = proc.k
     out = []
     fn = f'me_{proc.name}'
     out.append(f'// ---- {proc.name}: {k} gluons, {math.factorial(k)} colour orderings, '
                f'{2 ** (k + 2)} helicities')
     out.append(f'template <typename R, typename KT, typename Sink>')
+    lds_arg = ', R* __restrict__ lds' if lds_budget else ''
     out.append(f'__device__ __forceinline__ void {fn}_body(const KT (&p)[{proc.n_ext}][4], '
-               f'const KT mt, Sink& sink)')
+               f'const KT mt, Sink& sink{lds_arg})')
     out.append('{')
     # ---------------- prologue (double precision kinematics) ----------------
     pro = []
@@ -153,9 +167,9 @@ def emit_qcd(proc, with_colour=True):
                    f'q{n}[1] * q{n}[1] - q{n}[2] * q{n}[2] - mt2));')
     # momenta in working precision
     for gi in range(k):
-        pro.append(f'const R K{gi}[4] = {{cvt<R>(k{gi}[0]), cvt<R>(k{gi}[1]), cvt<R>(k{gi}[2]), '
+        pro.append(f'R K{gi}[4] = {{cvt<R>(k{gi}[0]), cvt<R>(k{gi}[1]), cvt<R>(k{gi}[2]), '
                    f'cvt<R>(k{gi}[3])}};')
-    pro.append('const R PT[4] = {cvt<R>(p[2][0]), cvt<R>(p[2][1]), cvt<R>(p[2][2]), cvt<R>(p[2][3])};')
+    pro.append('R PT[4] = {cvt<R>(p[2][0]), cvt<R>(p[2][1]), cvt<R>(p[2][2]), cvt<R>(p[2][3])};')
     pro.append('const R MT = cvt<R>(mt);')
     # outgoing-gluon polarisation bases (eps1/sqrt2, eps2/sqrt2)
     for gi, leg in enumerate(proc.gl_legs):
@@ -286,8 +300,24 @@ def emit_qcd(proc, with_colour=True):
             acc = csum(b, terms[mu])
             vec.append(cmat(b, C(b.mul(acc.re, ig), b.mul(acc.im, ig))))
         jmemo[rho] = vec
+        if rho in lds_slot:
+            for (mu, part), slot in lds_slot[rho].items():
+                v = vec[mu].re if part == 0 else vec[mu].im
+                b.lines.append(f'lds[{slot * 64}] = {b.ref(v)};')
         return vec
 
+    # LDS slots: canonical multi-gluon currents, longest first, within the budget;
+    # every current has 4 complex components (light-cone), all non-constant
+    lds_slot = {}
+    if lds_budget:
+        cands = [perm for r in range(k, 1, -1) for S_ in itertools.combinations(range(k), r)
+                 for perm in itertools.permutations(S_) if canon(perm) == perm]
+        nxt = 0
+        for perm in cands:
+            if nxt + 8 > lds_budget:
+                break
+            lds_slot[perm] = {(mu, part): nxt + 2 * mu + part for mu in range(4) for part in range(2)}
+            nxt += 8
     # build every gluon current (canonical orientations), by length
     for r in range(2, k + 1):
         for S_ in itertools.combinations(range(k), r):
@@ -298,8 +328,35 @@ def emit_qcd(proc, with_colour=True):
     gluon_lines = b.lines
     # ---------------- quark line (inside the top-helicity loop) ----------------
     q = Block('u')
-    # re-wrap names so the quark block references gluon-block values
     ub = [C(S(name=f'ubs[{j}].re'), S(name=f'ubs[{j}].im')) for j in range(4)]
+    qmoms = [Momentum(q, [S(name=f'K{gi}[{c}]') for c in range(4)]) for gi in range(k)]
+    for gi, leg in enumerate(proc.gl_legs):
+        if leg < 2:
+            E = S(name=f'K{gi}[0]')
+            qmoms[gi] = Momentum(q, [E, ZERO, ZERO, E if leg == 0 else q.neg(E)])
+    qsum_memo = {}
+
+    def QP(rho):
+        key = tuple(sorted(rho))
+        if key not in qsum_memo:
+            qsum_memo[key] = qmoms[key[0]] if len(key) == 1 else msum(q, [qmoms[i] for i in key], [1] * len(key))
+        return qsum_memo[key]
+    group_of = {}
+
+    def QJ(rho):
+        """Gluon current as seen from the quark line (re-read from LDS if parked there)."""
+        c = canon(rho)
+        if c not in lds_slot:
+            return J(rho)
+        sgn = 1 if c == rho else (-1) ** (len(rho) + 1)
+        vec = []
+        for mu in range(4):
+            parts = []
+            for part in range(2):
+                v = q.new(f'lds[{lds_slot[c][(mu, part)] * 64}]', 0)
+                parts.append(v if sgn > 0 else q.neg(v))
+            vec.append(C(parts[0], parts[1]))
+        return vec
 
     def slash_row(psi, Jv):
         """Terms of the row spinor psi * Jslash (light cone): list per component."""
@@ -318,14 +375,14 @@ def emit_qcd(proc, with_colour=True):
             return qmemo[prefix]
         terms = [[] for _ in range(4)]
         for s in range(len(prefix)):
-            rows = slash_row(Q(prefix[:s]), J(prefix[s:]))
+            rows = slash_row(Q(prefix[:s]), QJ(prefix[s:]))
             for c in range(4):
                 terms[c] += rows[c]
         psi = [cmat(q, csum(q, terms[c])) for c in range(4)]
         # propagator: (psi qslash + m psi)/(q^2 - m^2), q = p_t - P(prefix)
         n = _sname(sorted(prefix))
         iq = S(name=f'iq{n}')
-        Pp = P(prefix)
+        Pp = QP(prefix)
         qE = q.sub(S(name='PT[0]'), Pp.E)
         qx = q.sub(S(name='PT[1]'), Pp.x)
         qy = q.sub(S(name='PT[2]'), Pp.y)
@@ -347,10 +404,14 @@ def emit_qcd(proc, with_colour=True):
     # they were created in the gluon block (same scope in the emitted code), fine.
     vspin = [[C(S(name=f'vs[{h}][{j}].re'), S(name=f'vs[{h}][{j}].im')) for j in range(4)] for h in range(2)]
     amps = [[None] * len(proc.orderings) for _ in range(2)]
+    prev_first = None
     for si, sigma in enumerate(proc.orderings):
+        if group_barriers and prev_first is not None and sigma[0] != prev_first:
+            q.lines.append('__builtin_amdgcn_sched_barrier(0);')
+        prev_first = sigma[0]
         terms = [[] for _ in range(4)]
         for s in range(k):
-            rows = slash_row(Q(sigma[:s]), J(sigma[s:]))
+            rows = slash_row(Q(sigma[:s]), QJ(sigma[s:]))
             for c in range(4):
                 terms[c] += rows[c]
         full = [cmat(q, csum(q, terms[c])) for c in range(4)]
@@ -376,13 +437,23 @@ def emit_qcd(proc, with_colour=True):
 
     # ---------------- emit ----------------
     body = []
+    opq = []
+    if opaque_inputs:
+        for gi, leg in enumerate(proc.gl_legs):
+            comps = [0] if leg < 2 else [0, 1, 2, 3]
+            opq += [f'opaque(K{gi}[{c}]);' for c in comps]
+        opq += [f'opaque(PT[{c}]);' for c in range(4)]
     body.append('#pragma unroll 1')
     body.append(f'for (int gconf = 0; gconf < {2 ** k}; ++gconf) {{')
+    body += ['    ' + l for l in opq]
     for gi in range(k):
         body.append(f'    const R lam{gi} = (gconf >> {gi}) & 1 ? R(1) : R(-1);')
     body += ['    ' + l for l in gluon_lines]
     body.append('    #pragma unroll 1')
     body.append('    for (int ht = 0; ht < 2; ++ht) {')
+    body += ['        ' + l for l in opq]
+    if group_barriers:
+        body.append('        __builtin_amdgcn_sched_barrier(0);')
     body.append('        cplx<R> ubs[4];')
     body.append('        for (int j = 0; j < 4; ++j) ubs[j] = ht ? ub[1][j] : ub[0][j];')
     body += ['        ' + l for l in q.lines]
@@ -400,8 +471,9 @@ def emit_qcd(proc, with_colour=True):
     body.append('}')
     out += ['    ' + l for l in body]
     out.append('}')
-    if not with_colour:
-        return '\n'.join(out), None
+    nslots = 8 * len(lds_slot)
+    if not with_colour or not constants:
+        return '\n'.join(out), dict(lds_slots=nslots)
     out.append('')
     out.append(f'// normalisation: g^(2k) / (avg * sym * colour denominator)')
     out.append(f'__host__ __device__ constexpr double {fn}_norm_noalpha() '
@@ -412,7 +484,7 @@ def emit_qcd(proc, with_colour=True):
     flops = dict(gluon_per_gconf=gluon_flops, quark_per_top_hel=quark_flops,
                  colour_per_hel=colour_flops // 2,
                  per_event=(2 ** k) * (gluon_flops + 2 * quark_flops + colour_flops),
-                 helicities=helis)
+                 helicities=helis, lds_slots=nslots)
     out.append(f'// flops per event (generated count): {flops}')
     return '\n'.join(out), flops
 
@@ -421,14 +493,39 @@ def colour_table(proc):
     return proc.cnum, proc.cden
 
 
-def emit_all(outdir):
+# Per-lane LDS budgets (working-type scalars) for the LDS-parking variants:
+# at one wave per SIMD a wave may own 40 KB of the 160 KB LDS, i.e. 160 floats
+# or 80 doubles per lane.
+LDS_F32 = 152
+LDS_F64 = 72
+
+
+def _variant(proc, name, suffix, **kw):
+    src, info = emit_qcd(proc, **kw)
+    return src.replace(f'me_{name}_body', f'me_{name}_{suffix}', 1) if suffix != 'body' else src, info
+
+
+def emit_all(outdir, **opts):
     os.makedirs(outdir, exist_ok=True)
     summary = {}
     for name, n_ext in (('gg_tt', 4), ('gg_ttg', 5), ('gg_ttgg', 6)):
         proc = GGTTProcess(name, n_ext)
-        src, flops = emit_qcd(proc, with_colour=True)
-        src_a, _ = emit_qcd(proc, with_colour=False)
-        src_a = src_a.replace(f'me_{name}_body', f'me_{name}_amps')
+        src, flops = emit_qcd(proc, with_colour=True, **opts)
+        # large process: LDS-parking variants for the FP32 (VALU and matrix-core colour) and FP64 kernels
+        lds = n_ext >= 6
+        src_a, ia = _variant(proc, name, 'amps', with_colour=False, lds_budget=LDS_F32 if lds else 0, **opts)
+        extra = []
+        if lds:
+            s32, i32 = _variant(proc, name, 'body_lds32', with_colour=True, lds_budget=LDS_F32, constants=False,
+                                **opts)
+            s64, i64 = _variant(proc, name, 'body_lds64', with_colour=True, lds_budget=LDS_F64, constants=False,
+                                **opts)
+            extra = [s32, s64,
+                     f'constexpr int me_{name}_lds32_slots = {i32["lds_slots"]};',
+                     f'constexpr int me_{name}_lds64_slots = {i64["lds_slots"]};',
+                     f'constexpr int me_{name}_amps_slots = {ia["lds_slots"]};']
+            flops['lds_slots_f32'] = i32['lds_slots']
+            flops['lds_slots_f64'] = i64['lds_slots']
         cnum, cden = proc.cnum, proc.cden
         ctab = [f'// colour matrix numerators for {name} (denominator {cden})',
                 f'static __constant__ const short me_{name}_cnum[{len(cnum)}][{len(cnum)}] = {{']
@@ -438,7 +535,7 @@ def emit_all(outdir):
         ctab.append(f'constexpr int me_{name}_cden = {cden};')
         with open(os.path.join(outdir, f'me_{name}.inc'), 'w') as f:
             f.write('// Generated by paper_2211_14056_amd.gen.process_compiler -- do not edit.\n')
-            f.write(src + '\n\n' + src_a + '\n\n' + '\n'.join(ctab) + '\n')
+            f.write(src + '\n\n' + src_a + '\n\n' + '\n\n'.join(extra) + '\n\n' + '\n'.join(ctab) + '\n')
         summary[name] = flops
     with open(os.path.join(outdir, 'flops.txt'), 'w') as f:
         for name, fl in summary.items():

@@ -474,3 +474,13 @@ def test_autograd_function(h):
     assert _normwise(x.grad.cpu().numpy(), gx_o).max() < 1e-10
     assert abs(theta.grad[0].item() / gth_o[:, 0].sum() - 1) < 1e-10
     assert abs(theta.grad[1].item() / gth_o[:, 1].sum() - 1) < 1e-12
+
+
+def test_precision_errors(h):
+    ev = gpu_events(h, 'ee_mumu', 64, seed=1)
+    with pytest.raises(mf.MFError) as ei:      # no colour to contract for e+e- -> mu+mu-
+        mf.matrix_element(h, mf.MF_EE_MUMU, ev['p'], mf.MF_FP32_MFMA_F32)
+    assert ei.value.status == -2
+    with pytest.raises(mf.MFError) as ei:
+        mf.matrix_element(h, mf.MF_EE_MUMU, ev['p'], 7)
+    assert ei.value.status == -1
