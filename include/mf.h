@@ -106,6 +106,19 @@ const char* mf_last_error(void);
 int mf_process_legs(int proc);
 int mf_process_dims(int proc);
 
+/* Launch configuration (what the autotuner sets):
+ *   proc >= 0: threads per block for single-request launches of (proc,
+ *     precision), 64..256 in steps of 64, 0 = library default.  The
+ *     gg -> ttbar gg kernels always run one-wave blocks (their LDS is per wave)
+ *     and ignore it.  proc < 0 leaves the per-process settings unchanged.
+ *   batch_waves_per_cu > 0: grid of the persistent mixed-batch launch
+ *     (one-wave blocks per compute unit); <= 0 leaves it unchanged.
+ *   batch_persistent: 1 = several requests in one call share one persistent
+ *     launch (default), 0 = one launch per request, < 0 = unchanged.
+ * Errors: MF_ERR_INVALID_ARG for out-of-range values. */
+mf_status mf_set_launch(mf_handle h, int proc, int precision, int block, int batch_waves_per_cu,
+                        int batch_persistent);
+
 /* Number of Newton non-convergence events counted by the handle so far
  * (synchronises the handle's device). */
 mf_status mf_failures(mf_handle h, uint64_t* count);

@@ -61,6 +61,8 @@ def lib():
     L.mf_process_legs.argtypes = [I32]
     L.mf_process_dims.argtypes = [I32]
     L.mf_precision_available.argtypes = [I32]
+    L.mf_set_launch.argtypes = [VP, I32, I32, I32, I32, I32]
+    L.mf_set_launch.restype = I32
     L.mf_phase_space.argtypes = [VP, I32, ctypes.POINTER(mf_params), I64, VP, U64, U64, VP, VP, I32,
                                  VP, VP, VP, VP, VP, VP, VP]
     L.mf_matrix_element.argtypes = [VP, ctypes.POINTER(mf_request), I32, I32, ctypes.POINTER(mf_params), VP]
@@ -147,6 +149,10 @@ class Handle:
             self.close()
         except Exception:
             pass
+
+    def set_launch(self, proc=-1, precision=0, block=0, batch_waves_per_cu=0, batch_persistent=-1):
+        """mf_set_launch: per-(process, precision) block size and persistent-batch grid."""
+        _check(lib().mf_set_launch(self.h, proc, precision, block, batch_waves_per_cu, batch_persistent))
 
     def failures(self):
         c = ctypes.c_uint64()

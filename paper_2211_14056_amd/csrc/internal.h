@@ -50,6 +50,29 @@ bool precision_available(int precision);
 hipError_t launch_matrix_element_mfma(const MeJob& j, int precision, double mt, double coupling, int block,
                                       hipStream_t s);
 
+constexpr int MAX_BATCH = 64;
+
+struct BatchReq {
+    int proc;
+    int64_t n;
+    const double* p;
+    void* out;
+    int64_t tile_begin;     // first 64-event tile of this request
+};
+
+struct BatchArgs {
+    BatchReq req[MAX_BATCH];
+    int nreq;
+    int64_t ntiles;
+    unsigned* counter;      // device tile counter (reset by the launch)
+    double mt;
+    double coupling[4];     // per process: alpha (e+e-) or (4 pi alpha_s)^k
+};
+
+// One persistent launch over a mixed batch; precision as for
+// launch_matrix_element (gg processes only); grid = number of one-wave blocks.
+hipError_t launch_batch(const BatchArgs& a, int precision, int grid, hipStream_t s);
+
 struct VjpJob {
     int proc;
     int64_t n;

@@ -1,0 +1,10 @@
+// Instantiations of the persistent mixed-batch kernel (own translation unit
+// so the build compiles them in parallel).
+#include "me_batch_kernel.h"
+
+namespace mf {
+
+template hipError_t launch_batch_one<float, 1>(const BatchArgs&, int, hipStream_t);
+template hipError_t launch_batch_one<float, 2>(const BatchArgs&, int, hipStream_t);
+
+}  // namespace mf

@@ -36,9 +36,15 @@ bool valid_proc(int p) { return p >= MF_EE_MUMU && p <= MF_GG_TTGG; }
 
 struct mf_handle_s {
     int device = 0;
+    int n_cu = 256;
     double* partials = nullptr;
     size_t partials_cap = 0;           // doubles
     unsigned long long* fail_dev = nullptr;
+    unsigned* tile_counter = nullptr;  // persistent-batch work queue
+    // launch configuration (set by mf_set_launch / the autotuner)
+    int block[4][4];                   // [process][precision] threads per block, 0 = default
+    int batch_waves_per_cu = 4;        // persistent grid = waves_per_cu * n_cu one-wave blocks
+    int batch_persistent = 1;          // 0 = one launch per request instead
 };
 
 namespace {
@@ -98,8 +104,17 @@ mf_status mf_create(int device, mf_handle* out)
     DeviceGuard g(device);
     mf_handle h = new mf_handle_s;
     h->device = device;
+    for (auto& r : h->block)
+        for (int& b : r) b = 0;
+    {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+            h->n_cu = prop.multiProcessorCount;
+    }
     e = hipMalloc(&h->fail_dev, sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipMalloc(&h->tile_counter, sizeof(unsigned));
     if (e != hipSuccess) {
+        if (h->fail_dev) hipFree(h->fail_dev);
         delete h;
         return fail(MF_ERR_NO_MEMORY, "mf_create: cannot allocate counters");
     }
@@ -121,7 +136,29 @@ mf_status mf_destroy(mf_handle h)
     hipDeviceSynchronize();
     if (h->partials) hipFree(h->partials);
     if (h->fail_dev) hipFree(h->fail_dev);
+    if (h->tile_counter) hipFree(h->tile_counter);
     delete h;
+    return MF_OK;
+}
+
+mf_status mf_set_launch(mf_handle h, int proc, int precision, int block, int batch_waves_per_cu,
+                        int batch_persistent)
+{
+    g_err.clear();
+    if (!h) return fail(MF_ERR_INVALID_ARG, "mf_set_launch: NULL handle");
+    if (proc >= 0) {
+        if (!valid_proc(proc) || precision < MF_FP64 || precision > MF_FP32_MFMA_F32)
+            return fail(MF_ERR_INVALID_ARG, "mf_set_launch: bad process or precision");
+        if (block != 0 && (block < 64 || block > 256 || block % 64))
+            return fail(MF_ERR_INVALID_ARG, "mf_set_launch: block must be 64, 128, 192 or 256 (0 = default)");
+        h->block[proc][precision] = block;
+    }
+    if (batch_waves_per_cu > 0) {
+        if (batch_waves_per_cu > 16)
+            return fail(MF_ERR_INVALID_ARG, "mf_set_launch: batch_waves_per_cu must be in [1, 16]");
+        h->batch_waves_per_cu = batch_waves_per_cu;
+    }
+    if (batch_persistent >= 0) h->batch_persistent = batch_persistent ? 1 : 0;
     return MF_OK;
 }
 
@@ -212,10 +249,53 @@ mf_status mf_matrix_element(mf_handle h, const mf_request* reqs, int n_reqs, int
     mf_status st = check_requests("mf_matrix_element", reqs, n_reqs, precision, prm, false);
     if (st != MF_OK) return st;
     DeviceGuard g(h->device);
+    hipStream_t st_ = static_cast<hipStream_t>(stream);
+    // gg requests of a multi-request call go to one persistent launch
+    int order[3] = {MF_GG_TTGG, MF_GG_TTG, MF_GG_TT};   // most expensive first
+    bool batched[4096] = {false};
+    if (n_reqs > 1 && n_reqs <= 4096 && h->batch_persistent) {
+        mf::BatchArgs a{};
+        a.counter = h->tile_counter;
+        a.mt = prm->m_t;
+        for (int p = 0; p < 4; ++p) {
+            double c = 1.0;
+            for (int k = 0; k < mf::n_gluons(p); ++k) c *= 4.0 * 3.141592653589793238463 * prm->alpha_s;
+            a.coupling[p] = c;
+        }
+        auto flush = [&]() -> mf_status {
+            if (a.nreq == 0) return MF_OK;
+            const int grid = h->batch_waves_per_cu * h->n_cu;
+            hipError_t e = mf::launch_batch(a, precision, grid, st_);
+            if (e != hipSuccess) return hip_fail(e, "mf_matrix_element persistent launch");
+            a.nreq = 0;
+            a.ntiles = 0;
+            return MF_OK;
+        };
+        for (int proc : order)
+            for (int i = 0; i < n_reqs; ++i) {
+                const mf_request& r = reqs[i];
+                if (r.proc != proc || r.n == 0) continue;
+                if (a.nreq == mf::MAX_BATCH) {
+                    mf_status s2 = flush();
+                    if (s2 != MF_OK) return s2;
+                }
+                mf::BatchReq& q = a.req[a.nreq++];
+                q.proc = r.proc;
+                q.n = r.n;
+                q.p = r.p;
+                q.out = r.me_out;
+                q.tile_begin = a.ntiles;
+                a.ntiles += (r.n + 63) / 64;
+                batched[i] = true;
+            }
+        mf_status s2 = flush();
+        if (s2 != MF_OK) return s2;
+    }
     for (int i = 0; i < n_reqs; ++i) {
-        if (reqs[i].n == 0) continue;
+        if (reqs[i].n == 0 || (i < 4096 && batched[i])) continue;
         mf::MeJob j{reqs[i].proc, reqs[i].n, reqs[i].p, reqs[i].me_out};
-        hipError_t e = mf::launch_matrix_element(j, precision, prm->m_t, prm->alpha_s, prm->alpha, 0,
+        const int blk = h->block[reqs[i].proc][precision];
+        hipError_t e = mf::launch_matrix_element(j, precision, prm->m_t, prm->alpha_s, prm->alpha, blk,
                                                  static_cast<hipStream_t>(stream));
         if (e == hipErrorInvalidValue)
             return fail(MF_ERR_UNSUPPORTED, "mf_matrix_element: precision %d not available for process %d",

@@ -484,3 +484,119 @@ def test_precision_errors(h):
     with pytest.raises(mf.MFError) as ei:
         mf.matrix_element(h, mf.MF_EE_MUMU, ev['p'], 7)
     assert ei.value.status == -1
+
+
+# ------------------------------------------------------------------ a10: persistent batch, graphs, tuning
+def _mixed_requests(h, spec, precision, seed0=200):
+    reqs, outs, evs = [], [], []
+    for i, (proc, n) in enumerate(spec):
+        ev = gpu_events(h, proc, n, seed=seed0 + i)
+        out = torch.empty(n, dtype=torch.float64 if precision == mf.MF_FP64 else torch.float32, device='cuda')
+        reqs.append(mf.make_request(mf.PROCESS[proc], ev['p'], out))
+        outs.append(out)
+        evs.append(ev)
+    return reqs, outs, evs
+
+
+@pytest.mark.parametrize('prec', ['fp64', 'fp32', 'fp32_mfma_f32', 'fp32_mfma_bf16'])
+def test_persistent_batch_equals_separate_launches(h, prec):
+    from paper_2211_14056_amd.workloads import mixed_batch
+    spec = mixed_batch(12, seed=5, scale=0.004)
+    spec[0] = ('gg_ttgg', 1)
+    spec[1] = ('gg_tt', 65)
+    say('persistent batch', prec, spec)
+    P_ = mf.PRECISION[prec]
+    reqs, outs, evs = _mixed_requests(h, spec, P_)
+    h.set_launch(batch_persistent=1, batch_waves_per_cu=2)
+    mf.mf_matrix_element(h, reqs, P_, mf.params())
+    torch.cuda.synchronize()
+    a = [o.clone() for o in outs]
+    h.set_launch(batch_persistent=0)
+    mf.mf_matrix_element(h, reqs, P_, mf.params())
+    torch.cuda.synchronize()
+    h.set_launch(batch_persistent=1, batch_waves_per_cu=4)
+    # same generated body compiled into a different kernel: equal up to the
+    # rounding of a different instruction order
+    tol = 1e-13 if prec == 'fp64' else 1e-6
+    for x, y in zip(a, outs):
+        assert float(((x.double() - y.double()).abs() / y.double().abs()).max()) <= tol
+
+
+def test_mixed_batch_full_size_one_launch(h):
+    """The 64-request mixed workload at full size in one persistent launch, sampled against the oracle."""
+    from paper_2211_14056_amd.workloads import mixed_batch
+    spec = mixed_batch(64, seed=5)
+    say('mixed batch full size', sum(n for _, n in spec), 'events')
+    reqs, outs, evs = _mixed_requests(h, spec, mf.MF_FP32_MFMA_BF16)
+    mf.mf_matrix_element(h, reqs, mf.MF_FP32_MFMA_BF16, mf.params())
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(3)
+    for (proc, n), out, ev in zip(spec, outs, evs):
+        assert bool(torch.isfinite(out).all())
+    for i in rng.choice(len(spec), 6, replace=False):
+        proc, n = spec[i]
+        idx = torch.tensor(rng.choice(n, min(n, 4), replace=False), device='cuda')
+        ref = oracle_me(proc, evs[i]['p'][:, :, idx].cpu().numpy())
+        got = outs[i][idx].double().cpu().numpy()
+        ok = evs[i]['pass_'][idx].cpu().numpy().astype(bool)
+        assert np.abs(got / ref - 1)[ok].max() < 1e-3 if ok.any() else True
+
+
+def test_graph_replay_equals_eager(h):
+    from paper_2211_14056_amd.integrator import VegasIntegrator
+    say('graph replay gg_ttg')
+    vi = VegasIntegrator('gg_ttg', precision=mf.MF_FP32, n=50_000, batches=2, seed=9, handle=h)
+    eager = []
+    for _ in range(4):
+        vi.enqueue_iteration()
+        eager.append((vi.acc.clone(), vi.edges.clone()))
+        vi._record()
+    vi.reset()
+    vi.iterate(1)
+    g = vi.capture()
+    replayed = [(eager[0][0], eager[0][1])]
+    for _ in range(3):
+        g.replay()
+        torch.cuda.synchronize()
+        # unrelated eager work between replays
+        junk = torch.randn(1000, device='cuda').sum()
+        replayed.append((vi.acc.clone(), vi.edges.clone()))
+        vi._record()
+    for (a1, e1), (a2, e2) in zip(eager, replayed):
+        assert torch.equal(a1, a2) and torch.equal(e1, e2)
+
+
+def test_graph_vegas_gg_tt_cross_section(h):
+    from paper_2211_14056_amd.integrator import VegasIntegrator
+    say('graph vegas gg_tt')
+    vi = VegasIntegrator('gg_tt', precision=mf.MF_FP64, n=1_000_000, batches=1, seed=2, handle=h)
+    vi.iterate(1)
+    vi.capture()
+    vi.replay(4)
+    I, sig, chi2 = vi.estimate()
+    ref = closed_forms.gg_tt_sigma(P['sqrt_s'] ** 2, P['m_t'], P['alpha_s']) * closed_forms.GEV2_TO_PB
+    say('  sigma', I, '+-', sig, 'closed form', ref)
+    assert abs(I - ref) < 3 * sig
+
+
+def test_autotuner(h, tmp_path, monkeypatch):
+    from paper_2211_14056_amd import autotune
+    monkeypatch.setenv('MF_TUNE_CACHE', str(tmp_path / 'tune.json'))
+    say('autotune')
+    t = autotune.sweep_block(h, 'gg_ttg', mf.MF_FP32, 1 << 16)
+    assert set(t) == set(autotune.BLOCKS) and all(v > 0 for v in t.values())
+    used = autotune.tune(h, procs=('gg_tt',), precisions=(mf.MF_FP32,), n=1 << 16,
+                         batch=[('gg_tt', 3000), ('gg_ttg', 2000), ('gg_ttgg', 500)], mode='search')
+    assert len(used) == 2
+    import json
+    c = json.load(open(tmp_path / 'tune.json'))
+    assert any('batch' in k for k in c)
+    # tuned handle still gives the same numbers as the default one
+    ev = gpu_events(h, 'gg_ttg', 1000, seed=3)
+    h.set_launch(mf.MF_GG_TTG, mf.MF_FP32, 64)
+    a = mf.matrix_element(h, mf.MF_GG_TTG, ev['p'], mf.MF_FP32)
+    h.set_launch(mf.MF_GG_TTG, mf.MF_FP32, 0)
+    b = mf.matrix_element(h, mf.MF_GG_TTG, ev['p'], mf.MF_FP32)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    h.set_launch(batch_persistent=1, batch_waves_per_cu=4)
