@@ -33,6 +33,37 @@ NB = 50
 COPY_BYTES = 512 << 20
 
 
+def source_hash():
+    """Hash of everything that determines the kernels (sources, generator, generated code)."""
+    import hashlib
+    h = hashlib.sha256()
+    pkg = os.path.join(ROOT, 'paper_2211_14056_amd')
+    for sub in ('csrc', os.path.join('csrc', 'generated'), 'gen'):
+        d = os.path.join(pkg, sub)
+        for f in sorted(os.listdir(d)):
+            if f.endswith(('.hip', '.h', '.cpp', '.inc', '.py')):
+                h.update(f.encode())
+                h.update(open(os.path.join(d, f), 'rb').read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(precision_name):
+    """HBM bytes per matrix-element launch from the committed counter summary, or None
+    when the kernels have changed since the counters were taken."""
+    path = os.path.join(ROOT, 'profiles', 'me_gg_ttgg_hbm_traffic.md')
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if line.startswith('- ') and ':' in line:
+            k, v = line[2:].split(':', 1)
+            vals[k.strip()] = v.strip().strip('`')
+    if vals.get('source-hash') != source_hash():
+        return None
+    v = vals.get(f'traffic-bytes-per-launch {precision_name}')
+    return float(v) if v else None
+
+
 def flops_per_event(proc):
     """Generated-code flop count per event (recursion + colour sum, FMA = 2)."""
     path = os.path.join(ROOT, 'paper_2211_14056_amd', 'csrc', 'generated', 'flops.txt')
@@ -86,14 +117,15 @@ def run_path(mf, h, prm, precision, steps, warmup, seed):
     return dict(seconds=t1 - t0, me_ms=float(np.mean(me_ms)), me=me, pas=pas, acc=acc)
 
 
-def cpu_baseline(seed, budget_s=20.0):
+def cpu_baseline(seed, budget_s=45.0):
     """The FP64 oracle (colour-ordered mode) on the host cores, bounded sample."""
     from oracle import integrand, philox, processes, vegas as ovegas
     torch.set_num_threads(os.cpu_count() or 1)
     par = processes.DEFAULT_PARAMS
     d = processes.dims(PROC)
     n = 256
-    # warm-up and size the sample to roughly the time budget
+    # warm-up and size the sample from it (the small warm-up sample costs more
+    # per event, so the timed sample lands at roughly 10-30 s)
     x = philox.uniforms(seed, n, d)
     t0 = time.perf_counter()
     integrand.integrand(PROC, par, x)
@@ -128,6 +160,9 @@ def main():
               'accumulators per iteration, which is not built here.', file=sys.stderr)
         sys.exit(2)
     import paper_2211_14056_amd as mf
+    if not os.path.exists(mf.LIB_PATH):
+        from paper_2211_14056_amd import build as _b
+        _b.build()
     torch.cuda.init()
     h = mf.Handle(0)
     prm = mf.params()
@@ -139,7 +174,7 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
     if args.precision == 'auto':
-        prec = mf.MF_FP32_MFMA_F32
+        prec = mf.MF_FP32_MFMA_BF16
     else:
         prec = mf.PRECISION[args.precision]
     head = run_path(mf, h, prm, prec, args.steps, args.warmup, args.seed)
@@ -155,6 +190,7 @@ def main():
     me_ach = fl * BATCH / (head['me_ms'] * 1e-3)
     me_ach64 = fl * BATCH / (ref['me_ms'] * 1e-3)
     dt = 'f32'
+    pname = [k for k, v in mf.PRECISION.items() if v == prec][0]
     out = {
         'metric': METRIC,
         'value': ev_s,
@@ -170,15 +206,16 @@ def main():
         'data': 'synthetic',
         'config': {'workload': 'gg->ttbar gg at sqrt(s_hat)=1 TeV, m_t=173 GeV, alpha_s=0.118, gluon pT>20 GeV, '
                                '|eta|<2.5, DeltaR>0.4; 1e6-event batches, Vegas refined every 16 batches',
-                   'process': PROC, 'batch': BATCH, 'precision': [k for k, v in mf.PRECISION.items() if v == prec][0]},
+                   'process': PROC, 'batch': BATCH, 'precision': pname},
         'me_events_per_s': BATCH / (head['me_ms'] * 1e-3),
         'rel_err_fp32_vs_fp64': rel_stats,
         'fp64': {'value': ev_s64, 'ms_per_step': ref['seconds'] / args.steps * 1e3,
                  'me_events_per_s': BATCH / (ref['me_ms'] * 1e-3),
                  'roofline': {'bound': 'alu', 'achieved': me_ach64 / 1e12, 'peak': PEAK['f64'] / 1e12,
-                              'unit': 'TFLOP/s', 'frac': me_ach64 / PEAK['f64'], 'traffic': None}},
+                              'unit': 'TFLOP/s', 'frac': me_ach64 / PEAK['f64'],
+                              'traffic': measured_traffic('fp64')}},
         'roofline': {'bound': 'alu', 'achieved': me_ach / 1e12, 'peak': PEAK['f32'] / 1e12, 'unit': 'TFLOP/s',
-                     'frac': me_ach / PEAK['f32'], 'traffic': None,
+                     'frac': me_ach / PEAK['f32'], 'traffic': measured_traffic(pname),
                      'kernel': 'matrix element', 'flops_per_event': fl},
     }
     if not args.no_cpu_baseline:

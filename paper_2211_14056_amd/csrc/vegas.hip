@@ -11,8 +11,9 @@
 //    grid size that depends only on n);
 //  * per wave, lane k < d owns the histogram row of dimension k in LDS and
 //    adds the wave's 64 events in lane order;
-//  * block partials (sum F, sum F^2, histogram) go to a workspace, and one
-//    workgroup sums them in block order and then refines the grid.
+//  * block partials (sum F, sum F^2, histogram) go to a cell-major workspace,
+//    and one workgroup sums them (a wave per cell, fixed lane order and a
+//    fixed butterfly) and then refines the grid.
 // F = flux * w * J_vegas * ME * pass is formed here from the phase-space
 // weight, the Vegas Jacobian and the matrix element, so it never round-trips
 // through memory unless the caller asks for it.
@@ -71,17 +72,18 @@ __global__ __launch_bounds__(VB) void k_vegas_accumulate(VegasArgs a)
         }
         __syncthreads();
     }
-    const int stride = 2 + d * nb;
-    double* out = a.partials + (int64_t)blockIdx.x * stride;
+    // partials are cell-major, [cell][block], so the final reduction reads them coalesced
+    const int64_t nblk = gridDim.x;
+    double* out = a.partials + blockIdx.x;
     if (tid == 0) {
         out[0] = red[0][0];
-        out[1] = red[1][0];
+        out[nblk] = red[1][0];
     }
     for (int c = tid; c < d * nb; c += VB) {
         const int k = c / nb, b = c % nb;
         double s = 0.0;
         for (int w = 0; w < WAVES; ++w) s += hist[w][k][b];
-        out[2 + c] = s;
+        out[(2 + c) * nblk] = s;
     }
 }
 
@@ -126,13 +128,21 @@ __device__ void refine_dim(const double* h, double* edges, int nb, double alpha)
     edges[nb] = 1.0;
 }
 
-__global__ __launch_bounds__(VB) void k_vegas_finalize(VegasArgs a)
+constexpr int FB = 1024;          // finalize workgroup: 16 waves
+
+__global__ __launch_bounds__(FB) void k_vegas_finalize(VegasArgs a)
 {
-    const int stride = 2 + a.d * a.nb;
-    for (int c = threadIdx.x; c < stride; c += VB) {
+    // one wave per cell: lane l sums blocks l, l+64, ... in order, then a fixed
+    // xor-butterfly adds the 64 lane sums (same order every run)
+    const int cells = 2 + a.d * a.nb;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int c = wv; c < cells; c += FB / 64) {
+        const double* src = a.partials + (int64_t)c * a.nblk;
         double s = 0.0;
-        for (int b = 0; b < a.nblk; ++b) s += a.partials[(int64_t)b * stride + c];
-        a.acc[c] = a.accumulate ? a.acc[c] + s : s;
+        for (int b = lane; b < a.nblk; b += 64) s += src[b];
+#pragma unroll
+        for (int m = 32; m > 0; m >>= 1) s += __shfl_xor(s, m);
+        if (lane == 0) a.acc[c] = a.accumulate ? a.acc[c] + s : s;
     }
     __syncthreads();
     if (a.update_edges && threadIdx.x < a.d) {
@@ -159,7 +169,7 @@ hipError_t launch_vegas(const VegasArgs& a, hipStream_t s)
     hipLaunchKernelGGL(k_vegas_accumulate, dim3(a.nblk), dim3(VB), 0, s, a);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
-    hipLaunchKernelGGL(k_vegas_finalize, dim3(1), dim3(VB), 0, s, a);
+    hipLaunchKernelGGL(k_vegas_finalize, dim3(1), dim3(FB), 0, s, a);
     return hipGetLastError();
 }
 

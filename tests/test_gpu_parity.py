@@ -29,6 +29,10 @@ def say(*a):
 
 @pytest.fixture(scope='module')
 def h():
+    import os
+    if not os.path.exists(mf.LIB_PATH):
+        from paper_2211_14056_amd import build as _b
+        _b.build()
     torch.cuda.init()
     return mf.Handle(0)
 
