@@ -34,14 +34,14 @@ COPY_BYTES = 512 << 20
 
 
 def source_hash():
-    """Hash of everything that determines the kernels (sources, generator, generated code)."""
+    """Hash of everything the kernels are compiled from (hand-written and generated sources)."""
     import hashlib
     h = hashlib.sha256()
     pkg = os.path.join(ROOT, 'paper_2211_14056_amd')
-    for sub in ('csrc', os.path.join('csrc', 'generated'), 'gen'):
+    for sub in ('csrc', os.path.join('csrc', 'generated')):
         d = os.path.join(pkg, sub)
         for f in sorted(os.listdir(d)):
-            if f.endswith(('.hip', '.h', '.cpp', '.inc', '.py')):
+            if f.endswith(('.hip', '.h', '.cpp', '.inc')):
                 h.update(f.encode())
                 h.update(open(os.path.join(d, f), 'rb').read())
     return h.hexdigest()[:16]

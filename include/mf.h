@@ -109,8 +109,11 @@ int mf_process_dims(int proc);
 /* Launch configuration (what the autotuner sets):
  *   proc >= 0: threads per block for single-request launches of (proc,
  *     precision), 64..256 in steps of 64, 0 = library default.  The
- *     gg -> ttbar gg kernels always run one-wave blocks (their LDS is per wave)
- *     and ignore it.  proc < 0 leaves the per-process settings unchanged.
+ *     gg -> ttbar gg kernels always run one-wave blocks (their LDS is per wave);
+ *     for them the value selects the event layout instead: in FP64, 256 = four
+ *     lanes per event (colour orderings split by first gluon, gluon currents
+ *     shared within the quad), any other value = one lane per event (default).
+ *     proc < 0 leaves the per-process settings unchanged.
  *   batch_waves_per_cu > 0: grid of the persistent mixed-batch launch
  *     (one-wave blocks per compute unit); <= 0 leaves it unchanged.
  *   batch_persistent: 1 = several requests in one call share one persistent

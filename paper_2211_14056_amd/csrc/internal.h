@@ -49,6 +49,11 @@ bool precision_available(int precision);
 // `coupling` = (4 pi alpha_s)^k
 hipError_t launch_matrix_element_mfma(const MeJob& j, int precision, double mt, double coupling, int block,
                                       hipStream_t s);
+// g g -> t tbar g g in FP64 with four lanes per event; `coupling` = (4 pi alpha_s)^4
+hipError_t launch_ttgg_quad(const MeJob& j, double mt, double coupling, hipStream_t s);
+// launch-configuration value of mf_set_launch that selects the four-lanes-per-event
+// layout for g g -> t tbar g g in FP64
+constexpr int TTGG_QUAD_LAYOUT = 256;
 
 constexpr int MAX_BATCH = 64;
 

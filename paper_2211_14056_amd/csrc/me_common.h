@@ -145,6 +145,28 @@ __device__ __forceinline__ void opaque(float& x) { asm volatile("" : "+v"(x)); }
 __device__ __forceinline__ void opaque(double& x) { asm volatile("" : "+v"(x)); }
 template <typename T> __device__ __forceinline__ void opaque(Dual<T>& x) { opaque(x.v); opaque(x.t); }
 
+// Value held by lane (i + M) mod 4 of this lane's quad (lanes 4j..4j+3), by a
+// DPP quad permutation.  Every lane of the quad must be active.
+template <int M>
+__device__ __forceinline__ int quad_rot_bits(int x)
+{
+    constexpr int ctrl = ((0 + M) & 3) | (((1 + M) & 3) << 2) | (((2 + M) & 3) << 4) | (((3 + M) & 3) << 6);
+    return __builtin_amdgcn_update_dpp(0, x, ctrl, 0xF, 0xF, false);
+}
+template <int M>
+__device__ __forceinline__ float quad_rot(float x)
+{
+    return __builtin_bit_cast(float, quad_rot_bits<M>(__builtin_bit_cast(int, x)));
+}
+template <int M>
+__device__ __forceinline__ double quad_rot(double x)
+{
+    const unsigned long long v = __builtin_bit_cast(unsigned long long, x);
+    const unsigned lo = (unsigned)quad_rot_bits<M>((int)(unsigned)v);
+    const unsigned hi = (unsigned)quad_rot_bits<M>((int)(unsigned)(v >> 32));
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
 // Helicity-sum accumulator used by the VALU colour path.
 template <typename R>
 struct HelicitySum {

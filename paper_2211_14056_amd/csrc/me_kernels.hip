@@ -167,6 +167,8 @@ hipError_t launch_matrix_element(const MeJob& j, int precision, double mt, doubl
         const double g2 = 4.0 * kPi * alpha_s;
         for (int i = 0; i < n_gluons(j.proc); ++i) coupling *= g2;
     }
+    if (j.proc == GG_TTGG && precision == 0 && block == TTGG_QUAD_LAYOUT)
+        return launch_ttgg_quad(j, mt, coupling, s);
     if (block <= 0) block = 256;
     switch (precision) {
     case 0: return launch_valu<double>(j, mt, coupling, block, s);

@@ -91,6 +91,243 @@ def msum(b, moms, signs):
     return Momentum(b, comps)
 
 
+def assign_lds_slots(cands, budget):
+    """LDS slots for the currents in ``cands`` (in order) within ``budget`` scalars:
+    {current: {(mu, part): slot}}; every current has 4 complex light-cone components."""
+    slots, nxt = {}, 0
+    for perm in cands:
+        if nxt + 8 > budget:
+            break
+        slots[perm] = {(mu, part): nxt + 2 * mu + part for mu in range(4) for part in range(2)}
+        nxt += 8
+    return slots
+
+
+class Recursion:
+    """Colour-ordered Berends-Giele recursion over the gluons, emitted into IR blocks.
+
+    Gluon currents go to block ``b`` (outside the top-helicity loop) and the
+    quark line to the block given to ``start_quark_line`` (inside it).  ``moms``
+    are the gluon momenta (incoming convention) and ``eps`` the external
+    currents, both indexed by gluon label; ``lds_slot`` maps the canonical
+    currents parked in LDS to their slots.
+    """
+
+    def __init__(self, b, moms, eps, lds_slot, stream=False, local_memo=False, remote=None):
+        self.b, self.moms, self.eps, self.lds_slot = b, moms, eps, lds_slot
+        self.stream = stream
+        self.local_memo = local_memo
+        # remote(rho) -> None, or (t, M, sign): J(rho) = sign * [J(t) of the lane M places
+        # further in the quad] (lanes that share an event, see lane_split)
+        self.remote = remote
+        self.msum_memo, self.dot_memo, self.jmemo = {}, {}, {}
+
+    @staticmethod
+    def canon(rho):
+        return rho if rho[0] < rho[-1] or len(rho) == 1 else tuple(reversed(rho))
+
+    def orient(self, rho):
+        """(canonical orientation, sign) with J(rho) = sign * J(canonical)."""
+        c = self.canon(rho)
+        return c, (1 if c == rho else (-1) ** (len(rho) + 1))
+
+    def P(self, rho):
+        """Momentum sum of a gluon subset (memoised)."""
+        key = tuple(sorted(rho))
+        if key not in self.msum_memo:
+            if len(key) == 1:
+                self.msum_memo[key] = self.moms[key[0]]
+            else:
+                self.msum_memo[key] = msum(self.b, [self.moms[i] for i in key], [1] * len(key))
+        return self.msum_memo[key]
+
+    def D(self, x, y):
+        """2 J(x).J(y), memoised over canonical orientations."""
+        b = self.b
+        (cx, sx), (cy, sy) = self.orient(x), self.orient(y)
+        key = (cx, cy) if cx <= cy else (cy, cx)
+        if key not in self.dot_memo:
+            self.dot_memo[key] = cmat(b, lc_dot2(b, self.J(cx), self.J(cy)))
+        v = self.dot_memo[key]
+        return v if sx * sy > 0 else cneg(b, v)
+
+    def J(self, rho):
+        """Off-shell gluon current of the ordered gluon sequence ``rho``."""
+        b = self.b
+        c = self.canon(rho)
+        if c != rho:
+            sgn = (-1) ** (len(rho) + 1)
+            v = self.J(c)
+            return v if sgn > 0 else [cneg(b, x) for x in v]
+        if rho in self.jmemo:
+            return self.jmemo[rho]
+        if len(rho) == 1:
+            self.jmemo[rho] = self.eps[rho[0]]
+            return self.jmemo[rho]
+        far = self.remote(rho) if self.remote else None
+        vec = self._received(*far) if far else self._vertices(rho)
+        self.jmemo[rho] = vec
+        if rho in self.lds_slot:
+            for (mu, part), slot in self.lds_slot[rho].items():
+                v = vec[mu].re if part == 0 else vec[mu].im
+                b.lines.append(f'lds[{slot * 64}] = {b.ref(v)};')
+        return vec
+
+    def _received(self, t, m, sign):
+        """Current read from another lane of the quad (DPP), with a reflection sign."""
+        b = self.b
+        own = self.J(t)
+
+        def rot(x):
+            if x.is_const:
+                return x
+            v = b.new(f'quad_rot<{m}>({b.ref(x)})', 0)
+            return v if sign > 0 else b.neg(v)
+        return [C(rot(x.re), rot(x.im)) for x in own]
+
+    def _vertices(self, rho):
+        """Current from the three- and four-gluon vertex splits of rho."""
+        b = self.b
+        J, P, D = self.J, self.P, self.D
+        if self.local_memo:
+            # build the sub-currents first, then forget dot products and momentum sums
+            # of earlier currents: recomputed here rather than kept live in between
+            for s in range(1, len(rho)):
+                J(rho[:s]), J(rho[s:])
+            self.dot_memo, self.msum_memo = {}, {}
+        terms = [[] for _ in range(4)]
+        acc = [None] * 4
+
+        def flush():
+            # stream mode: fold the terms gathered so far into the running sums, so the
+            # coefficients of one split die before the next split's are formed (same
+            # operations in the same order as one chain over all terms)
+            if self.stream:
+                for mu in range(4):
+                    acc[mu] = csum(b, terms[mu], acc[mu])
+                    terms[mu] = []
+        # three-vertex splits
+        for s in range(1, len(rho)):
+            a, bb = rho[:s], rho[s:]
+            Ja, Jb = J(a), J(bb)
+            Pa, Pb = P(a).lc(), P(bb).lc()
+            dab = D(a, bb)
+            hd = C(b.mul(dab.re, const(0.5)), b.mul(dab.im, const(0.5)))
+            hd = cmat(b, hd)
+            pbja = cmat(b, lc_dot2(b, Pb, Ja))        # 2 Pb.Ja
+            pajb = cmat(b, lc_dot2(b, Pa, Jb))        # 2 Pa.Jb
+            for mu in range(4):
+                dP = csub(b, Pa[mu], Pb[mu])
+                terms[mu].append((hd, dP))
+                terms[mu].append((pbja, Jb[mu]))
+                terms[mu].append((cneg(b, pajb), Ja[mu]))
+            flush()
+        # four-vertex splits
+        for s1 in range(1, len(rho) - 1):
+            for s2 in range(s1 + 1, len(rho)):
+                a, bb, cc = rho[:s1], rho[s1:s2], rho[s2:]
+                Ja, Jb, Jc = J(a), J(bb), J(cc)
+                dac = D(a, cc)
+                dab = D(a, bb)
+                dbc = D(bb, cc)
+                hab = cmat(b, C(b.mul(dab.re, const(-0.5)), b.mul(dab.im, const(-0.5))))
+                hbc = cmat(b, C(b.mul(dbc.re, const(-0.5)), b.mul(dbc.im, const(-0.5))))
+                for mu in range(4):
+                    terms[mu].append((dac, Jb[mu]))
+                    terms[mu].append((hab, Jc[mu]))
+                    terms[mu].append((hbc, Ja[mu]))
+                flush()
+        ig = S(name=f'ig{_sname(sorted(rho))}')
+        vec = []
+        for mu in range(4):
+            tot = acc[mu] if self.stream else csum(b, terms[mu])
+            vec.append(cmat(b, C(b.mul(tot.re, ig), b.mul(tot.im, ig))))
+        return vec
+
+    # ------------------------------------------------------------ quark line
+    def start_quark_line(self, q, qmoms, ub):
+        """Quark-line block ``q``, the gluon momenta as seen there, and the row spinor ubar."""
+        self.q, self.qmoms = q, qmoms
+        self.qsum_memo = {}
+        self.qmemo = {(): ub}
+
+    def QP(self, rho):
+        key = tuple(sorted(rho))
+        if key not in self.qsum_memo:
+            self.qsum_memo[key] = (self.qmoms[key[0]] if len(key) == 1 else
+                                   msum(self.q, [self.qmoms[i] for i in key], [1] * len(key)))
+        return self.qsum_memo[key]
+
+    def QJ(self, rho):
+        """Gluon current as seen from the quark line (re-read from LDS if parked there)."""
+        q = self.q
+        c = self.canon(rho)
+        if c not in self.lds_slot:
+            return self.J(rho)
+        sgn = 1 if c == rho else (-1) ** (len(rho) + 1)
+        vec = []
+        for mu in range(4):
+            parts = []
+            for part in range(2):
+                v = q.new(f'lds[{self.lds_slot[c][(mu, part)] * 64}]', 0)
+                parts.append(v if sgn > 0 else q.neg(v))
+            vec.append(C(parts[0], parts[1]))
+        return vec
+
+    def slash_row(self, psi, Jv):
+        """Terms of the row spinor psi * Jslash (light cone): list per component."""
+        q = self.q
+        Jp, Jm, Jt, Jtb = Jv
+        return [
+            [(psi[2], Jp), (psi[3], Jt)],
+            [(psi[2], Jtb), (psi[3], Jm)],
+            [(psi[0], Jm), (cneg(q, psi[1]), Jt)],
+            [(cneg(q, psi[0]), Jtb), (psi[1], Jp)],
+        ]
+
+    def Q(self, prefix):
+        """Row spinor ubar Jslash .. S(q) after the gluons of ``prefix`` (propagator included)."""
+        if prefix in self.qmemo:
+            return self.qmemo[prefix]
+        q = self.q
+        terms = [[] for _ in range(4)]
+        for s in range(len(prefix)):
+            rows = self.slash_row(self.Q(prefix[:s]), self.QJ(prefix[s:]))
+            for c in range(4):
+                terms[c] += rows[c]
+        psi = [cmat(q, csum(q, terms[c])) for c in range(4)]
+        # propagator: (psi qslash + m psi)/(q^2 - m^2), q = p_t - P(prefix)
+        n = _sname(sorted(prefix))
+        iq = S(name=f'iq{n}')
+        Pp = self.QP(prefix)
+        qE = q.sub(S(name='PT[0]'), Pp.E)
+        qx = q.sub(S(name='PT[1]'), Pp.x)
+        qy = q.sub(S(name='PT[2]'), Pp.y)
+        qz = q.sub(S(name='PT[3]'), Pp.z)
+        qp = q.mul(q.add(qE, qz), iq)
+        qm = q.mul(q.sub(qE, qz), iq)
+        qxs = q.mul(qx, iq)
+        qys = q.mul(qy, iq)
+        ms = q.mul(S(name='MT'), iq)
+        qlc = [C(qp), C(qm), C(qxs, qys), C(qxs, q.neg(qys))]
+        rows = self.slash_row(psi, qlc)
+        out_ = []
+        for c in range(4):
+            out_.append(cmat(q, csum(q, rows[c] + [(psi[c], C(ms))])))
+        self.qmemo[prefix] = out_
+        return out_
+
+    def closing(self, sigma):
+        """Open row spinor of the full ordering: sum over the last block of Q(prefix) Jslash(block)."""
+        q = self.q
+        terms = [[] for _ in range(4)]
+        for s in range(len(sigma)):
+            rows = self.slash_row(self.Q(sigma[:s]), self.QJ(sigma[s:]))
+            for c in range(4):
+                terms[c] += rows[c]
+        return [cmat(q, csum(q, terms[c])) for c in range(4)]
+
+
 # ----------------------------------------------------------------- process
 class GGTTProcess:
     """g(0) g(1) -> t(2) tbar(3) g(4) ... g(n_ext-1)."""
@@ -118,7 +355,8 @@ def _sname(sub):
     return ''.join(str(i) for i in sub)
 
 
-def emit_qcd(proc, with_colour=True, opaque_inputs=True, group_barriers=True, lds_budget=0, constants=True):
+def emit_qcd(proc, with_colour=True, opaque_inputs=True, group_barriers=True, lds_budget=0, constants=True,
+             barrier_every=0, stream=False):
     """Return (source text, flop counts) of the device function for ``proc``.
 
     opaque_inputs: re-declare the momenta as opaque at the top of each helicity
@@ -132,6 +370,10 @@ def emit_qcd(proc, with_colour=True, opaque_inputs=True, group_barriers=True, ld
       slots when computed and re-read at each use on the quark line, so they do
       not occupy registers across the top-helicity loop.  The emitted body then
       takes an LDS pointer (this lane's column, stride 64) as extra argument.
+    barrier_every: if > 0, a scheduling barrier after every that many emitted
+      statements, which pins the instruction order close to the emission order.
+    stream: fold each vertex split of a gluon current into running sums as soon
+      as its coefficients are formed (fewer values live at once; same arithmetic).
     """
     k = proc.k
     out = []
@@ -219,111 +461,18 @@ def emit_qcd(proc, with_colour=True, opaque_inputs=True, group_barriers=True, ld
             tbr = b.sumprod([(l, b.neg(ux))], wy)
             tbi = b.sumprod([(l, uy)], wx)
             eps.append([C(ez), C(b.neg(ez)), C(tr, ti), C(tbr, tbi)])
-    # momentum sums of gluon subsets (light cone), memoised
-    msum_memo = {}
-
-    def P(rho):
-        key = tuple(sorted(rho))
-        if key not in msum_memo:
-            if len(key) == 1:
-                msum_memo[key] = moms[key[0]]
-            else:
-                msum_memo[key] = msum(b, [moms[i] for i in key], [1] * len(key))
-        return msum_memo[key]
-
-    dot_memo = {}
-
-    def orient(rho):
-        """(canonical orientation, sign) with J(rho) = sign * J(canonical)."""
-        c = canon(rho)
-        return c, (1 if c == rho else (-1) ** (len(rho) + 1))
-
-    def D(x, y):
-        """2 J(x).J(y), memoised over canonical orientations."""
-        (cx, sx), (cy, sy) = orient(x), orient(y)
-        key = (cx, cy) if cx <= cy else (cy, cx)
-        if key not in dot_memo:
-            dot_memo[key] = cmat(b, lc_dot2(b, J(cx), J(cy)))
-        v = dot_memo[key]
-        return v if sx * sy > 0 else cneg(b, v)
-
-    # gluon currents
-    jmemo = {}
-
-    def canon(rho):
-        return rho if rho[0] < rho[-1] or len(rho) == 1 else tuple(reversed(rho))
-
-    def J(rho):
-        c = canon(rho)
-        if c != rho:
-            sgn = (-1) ** (len(rho) + 1)
-            v = J(c)
-            return v if sgn > 0 else [cneg(b, x) for x in v]
-        if rho in jmemo:
-            return jmemo[rho]
-        if len(rho) == 1:
-            jmemo[rho] = eps[rho[0]]
-            return jmemo[rho]
-        terms = [[] for _ in range(4)]
-        # three-vertex splits
-        for s in range(1, len(rho)):
-            a, bb = rho[:s], rho[s:]
-            Ja, Jb = J(a), J(bb)
-            Pa, Pb = P(a).lc(), P(bb).lc()
-            dab = D(a, bb)
-            hd = C(b.mul(dab.re, const(0.5)), b.mul(dab.im, const(0.5)))
-            hd = cmat(b, hd)
-            pbja = cmat(b, lc_dot2(b, Pb, Ja))        # 2 Pb.Ja
-            pajb = cmat(b, lc_dot2(b, Pa, Jb))        # 2 Pa.Jb
-            for mu in range(4):
-                dP = csub(b, Pa[mu], Pb[mu])
-                terms[mu].append((hd, dP))
-                terms[mu].append((pbja, Jb[mu]))
-                terms[mu].append((cneg(b, pajb), Ja[mu]))
-        # four-vertex splits
-        for s1 in range(1, len(rho) - 1):
-            for s2 in range(s1 + 1, len(rho)):
-                a, bb, cc = rho[:s1], rho[s1:s2], rho[s2:]
-                Ja, Jb, Jc = J(a), J(bb), J(cc)
-                dac = D(a, cc)
-                dab = D(a, bb)
-                dbc = D(bb, cc)
-                hab = cmat(b, C(b.mul(dab.re, const(-0.5)), b.mul(dab.im, const(-0.5))))
-                hbc = cmat(b, C(b.mul(dbc.re, const(-0.5)), b.mul(dbc.im, const(-0.5))))
-                for mu in range(4):
-                    terms[mu].append((dac, Jb[mu]))
-                    terms[mu].append((hab, Jc[mu]))
-                    terms[mu].append((hbc, Ja[mu]))
-        ig = S(name=f'ig{_sname(sorted(rho))}')
-        vec = []
-        for mu in range(4):
-            acc = csum(b, terms[mu])
-            vec.append(cmat(b, C(b.mul(acc.re, ig), b.mul(acc.im, ig))))
-        jmemo[rho] = vec
-        if rho in lds_slot:
-            for (mu, part), slot in lds_slot[rho].items():
-                v = vec[mu].re if part == 0 else vec[mu].im
-                b.lines.append(f'lds[{slot * 64}] = {b.ref(v)};')
-        return vec
-
-    # LDS slots: canonical multi-gluon currents, longest first, within the budget;
-    # every current has 4 complex components (light-cone), all non-constant
     lds_slot = {}
     if lds_budget:
         cands = [perm for r in range(k, 1, -1) for S_ in itertools.combinations(range(k), r)
-                 for perm in itertools.permutations(S_) if canon(perm) == perm]
-        nxt = 0
-        for perm in cands:
-            if nxt + 8 > lds_budget:
-                break
-            lds_slot[perm] = {(mu, part): nxt + 2 * mu + part for mu in range(4) for part in range(2)}
-            nxt += 8
+                 for perm in itertools.permutations(S_) if Recursion.canon(perm) == perm]
+        lds_slot = assign_lds_slots(cands, lds_budget)
+    rec = Recursion(b, moms, eps, lds_slot, stream=stream)
     # build every gluon current (canonical orientations), by length
     for r in range(2, k + 1):
         for S_ in itertools.combinations(range(k), r):
             for perm in itertools.permutations(S_):
-                if canon(perm) == perm:
-                    J(perm)
+                if Recursion.canon(perm) == perm:
+                    rec.J(perm)
     gluon_flops = b.flops
     gluon_lines = b.lines
     # ---------------- quark line (inside the top-helicity loop) ----------------
@@ -334,74 +483,7 @@ def emit_qcd(proc, with_colour=True, opaque_inputs=True, group_barriers=True, ld
         if leg < 2:
             E = S(name=f'K{gi}[0]')
             qmoms[gi] = Momentum(q, [E, ZERO, ZERO, E if leg == 0 else q.neg(E)])
-    qsum_memo = {}
-
-    def QP(rho):
-        key = tuple(sorted(rho))
-        if key not in qsum_memo:
-            qsum_memo[key] = qmoms[key[0]] if len(key) == 1 else msum(q, [qmoms[i] for i in key], [1] * len(key))
-        return qsum_memo[key]
-    group_of = {}
-
-    def QJ(rho):
-        """Gluon current as seen from the quark line (re-read from LDS if parked there)."""
-        c = canon(rho)
-        if c not in lds_slot:
-            return J(rho)
-        sgn = 1 if c == rho else (-1) ** (len(rho) + 1)
-        vec = []
-        for mu in range(4):
-            parts = []
-            for part in range(2):
-                v = q.new(f'lds[{lds_slot[c][(mu, part)] * 64}]', 0)
-                parts.append(v if sgn > 0 else q.neg(v))
-            vec.append(C(parts[0], parts[1]))
-        return vec
-
-    def slash_row(psi, Jv):
-        """Terms of the row spinor psi * Jslash (light cone): list per component."""
-        Jp, Jm, Jt, Jtb = Jv
-        return [
-            [(psi[2], Jp), (psi[3], Jt)],
-            [(psi[2], Jtb), (psi[3], Jm)],
-            [(psi[0], Jm), (cneg(q, psi[1]), Jt)],
-            [(cneg(q, psi[0]), Jtb), (psi[1], Jp)],
-        ]
-
-    qmemo = {(): ub}
-
-    def Q(prefix):
-        if prefix in qmemo:
-            return qmemo[prefix]
-        terms = [[] for _ in range(4)]
-        for s in range(len(prefix)):
-            rows = slash_row(Q(prefix[:s]), QJ(prefix[s:]))
-            for c in range(4):
-                terms[c] += rows[c]
-        psi = [cmat(q, csum(q, terms[c])) for c in range(4)]
-        # propagator: (psi qslash + m psi)/(q^2 - m^2), q = p_t - P(prefix)
-        n = _sname(sorted(prefix))
-        iq = S(name=f'iq{n}')
-        Pp = QP(prefix)
-        qE = q.sub(S(name='PT[0]'), Pp.E)
-        qx = q.sub(S(name='PT[1]'), Pp.x)
-        qy = q.sub(S(name='PT[2]'), Pp.y)
-        qz = q.sub(S(name='PT[3]'), Pp.z)
-        qp = q.mul(q.add(qE, qz), iq)
-        qm = q.mul(q.sub(qE, qz), iq)
-        qxs = q.mul(qx, iq)
-        qys = q.mul(qy, iq)
-        ms = q.mul(S(name='MT'), iq)
-        qlc = [C(qp), C(qm), C(qxs, qys), C(qxs, q.neg(qys))]
-        rows = slash_row(psi, qlc)
-        out_ = []
-        for c in range(4):
-            out_.append(cmat(q, csum(q, rows[c] + [(psi[c], C(ms))])))
-        qmemo[prefix] = out_
-        return out_
-
-    # momentum sums used in the quark block must live in the quark block's namespace;
-    # they were created in the gluon block (same scope in the emitted code), fine.
+    rec.start_quark_line(q, qmoms, ub)
     vspin = [[C(S(name=f'vs[{h}][{j}].re'), S(name=f'vs[{h}][{j}].im')) for j in range(4)] for h in range(2)]
     amps = [[None] * len(proc.orderings) for _ in range(2)]
     prev_first = None
@@ -409,12 +491,7 @@ def emit_qcd(proc, with_colour=True, opaque_inputs=True, group_barriers=True, ld
         if group_barriers and prev_first is not None and sigma[0] != prev_first:
             q.lines.append('__builtin_amdgcn_sched_barrier(0);')
         prev_first = sigma[0]
-        terms = [[] for _ in range(4)]
-        for s in range(k):
-            rows = slash_row(Q(sigma[:s]), QJ(sigma[s:]))
-            for c in range(4):
-                terms[c] += rows[c]
-        full = [cmat(q, csum(q, terms[c])) for c in range(4)]
+        full = rec.closing(sigma)
         for h in range(2):
             amps[h][si] = cmat(q, csum(q, [(full[c], vspin[h][c]) for c in range(4)]))
     quark_flops = q.flops
@@ -436,6 +513,17 @@ def emit_qcd(proc, with_colour=True, opaque_inputs=True, group_barriers=True, ld
     colour_flops = cs.flops
 
     # ---------------- emit ----------------
+    def fence(lines):
+        if not barrier_every:
+            return lines
+        res = []
+        for i, l in enumerate(lines):
+            res.append(l)
+            if (i + 1) % barrier_every == 0:
+                res.append('__builtin_amdgcn_sched_barrier(0);')
+        return res
+    gluon_lines = fence(gluon_lines)
+    q.lines = fence(q.lines)
     body = []
     opq = []
     if opaque_inputs:
@@ -483,7 +571,7 @@ def emit_qcd(proc, with_colour=True, opaque_inputs=True, group_barriers=True, ld
     helis = 2 ** (k + 2)
     flops = dict(gluon_per_gconf=gluon_flops, quark_per_top_hel=quark_flops,
                  colour_per_hel=colour_flops // 2,
-                 per_event=(2 ** k) * (gluon_flops + 2 * quark_flops + colour_flops),
+                 per_event=(2 ** k) * (gluon_flops + 2 * (quark_flops + colour_flops)),
                  helicities=helis, lds_slots=nslots)
     out.append(f'// flops per event (generated count): {flops}')
     return '\n'.join(out), flops
@@ -536,6 +624,16 @@ def emit_all(outdir, **opts):
         with open(os.path.join(outdir, f'me_{name}.inc'), 'w') as f:
             f.write('// Generated by paper_2211_14056_amd.gen.process_compiler -- do not edit.\n')
             f.write(src + '\n\n' + src_a + '\n\n' + '\n\n'.join(extra) + '\n\n' + '\n'.join(ctab) + '\n')
+        if proc.k == 4:
+            # four lanes per event (FP64 kernel), in a file of its own
+            from . import lane_split
+            src_q, info_q = lane_split.emit_split(proc, LDS_F64)
+            with open(os.path.join(outdir, f'me_{name}_quad.inc'), 'w') as f:
+                f.write('// Generated by paper_2211_14056_amd.gen.lane_split -- do not edit.\n')
+                f.write(src_q + '\n\n' + f'constexpr int me_{name}_quad_slots = {info_q["lds_slots"]};\n')
+                f.write(f'__host__ __device__ constexpr double me_{name}_quad_norm_noalpha() '
+                        f'{{ return 1.0 / ({proc.avg!r} * {float(proc.sym)!r} * {float(proc.cden)!r}); }}\n')
+            flops['quad_executed_per_event'] = info_q['executed_per_event']
         summary[name] = flops
     with open(os.path.join(outdir, 'flops.txt'), 'w') as f:
         for name, fl in summary.items():

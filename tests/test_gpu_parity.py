@@ -263,6 +263,48 @@ def test_me_empty_and_tiny_batches(h):
             assert np.abs(me.cpu().numpy() / ref - 1).max() < 1e-12
 
 
+def _quad_me(h, p):
+    """FP64 gg -> ttbar gg with the four-lanes-per-event layout."""
+    h.set_launch(mf.MF_GG_TTGG, mf.MF_FP64, 256)
+    try:
+        return mf.matrix_element(h, mf.MF_GG_TTGG, p, mf.MF_FP64)
+    finally:
+        h.set_launch(mf.MF_GG_TTGG, mf.MF_FP64, 64)
+
+
+@pytest.mark.parametrize('n', [1, 15, 16, 17, ME_N['gg_ttgg'] + 3])
+def test_me_ttgg_quad_layout_vs_oracle(h, n):
+    """Four lanes per event (orderings split by first gluon, DPP colour exchange) vs the oracle,
+    with batches that end inside a workgroup of 16 events."""
+    say('me ttgg quad layout', n)
+    ev = gpu_events(h, 'gg_ttgg', n, seed=31)
+    me = _quad_me(h, ev['p'])
+    torch.cuda.synchronize()
+    ref = oracle_me('gg_ttgg', ev['p'].cpu().numpy())
+    rel = np.abs(me.cpu().numpy() / ref - 1)
+    say('  max rel', rel.max())
+    assert rel.max() < 1e-12
+
+
+def test_me_ttgg_quad_layout_full_size(h):
+    """At the benchmark batch size: quad layout equals the one-lane FP64 kernel to rounding
+    on every event, and sampled events match the oracle; an empty batch is a no-op."""
+    n = 1_000_000
+    say('me ttgg quad layout full size', n)
+    ev = gpu_events(h, 'gg_ttgg', n, seed=4)
+    a = _quad_me(h, ev['p'])
+    b = mf.matrix_element(h, mf.MF_GG_TTGG, ev['p'], mf.MF_FP64)
+    torch.cuda.synchronize()
+    rel = ((a / b) - 1).abs()
+    say('  quad vs one-lane max rel', float(rel.max()))
+    assert float(rel.max()) < 1e-12
+    idx = np.concatenate([np.random.default_rng(3).choice(n, 16, replace=False), [0, n - 1]])
+    ref = oracle_me('gg_ttgg', ev['p'][:, :, torch.tensor(idx, device=a.device)].cpu().numpy())
+    assert np.abs(a[torch.tensor(idx, device=a.device)].cpu().numpy() / ref - 1).max() < 1e-12
+    e = _quad_me(h, torch.empty(6, 4, 0, dtype=torch.float64, device='cuda'))
+    assert e.shape == (0,)
+
+
 # ------------------------------------------------------------------ a7-a8: Vegas
 def test_vegas_refine_vs_oracle(h):
     proc = 'gg_ttg'
