@@ -586,6 +586,9 @@ def colour_table(proc):
 # or 80 doubles per lane.
 LDS_F32 = 152
 LDS_F64 = 72
+# The four-lanes-per-event FP64 kernel runs two waves per compute unit: 80 KB of
+# LDS per wave, 160 doubles per lane.
+LDS_QUAD_F64 = 152
 
 
 def _variant(proc, name, suffix, **kw):
@@ -627,7 +630,7 @@ def emit_all(outdir, **opts):
         if proc.k == 4:
             # four lanes per event (FP64 kernel), in a file of its own
             from . import lane_split
-            src_q, info_q = lane_split.emit_split(proc, LDS_F64)
+            src_q, info_q = lane_split.emit_split(proc, LDS_QUAD_F64, local_memo=True)
             with open(os.path.join(outdir, f'me_{name}_quad.inc'), 'w') as f:
                 f.write('// Generated by paper_2211_14056_amd.gen.lane_split -- do not edit.\n')
                 f.write(src_q + '\n\n' + f'constexpr int me_{name}_quad_slots = {info_q["lds_slots"]};\n')
