@@ -128,23 +128,24 @@ __device__ void refine_dim(const double* h, double* edges, int nb, double alpha)
     edges[nb] = 1.0;
 }
 
-constexpr int FB = 1024;          // finalize workgroup: 16 waves
-
-__global__ __launch_bounds__(FB) void k_vegas_finalize(VegasArgs a)
+__global__ __launch_bounds__(64) void k_vegas_reduce(VegasArgs a)
 {
-    // one wave per cell: lane l sums blocks l, l+64, ... in order, then a fixed
-    // xor-butterfly adds the 64 lane sums (same order every run)
-    const int cells = 2 + a.d * a.nb;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int c = wv; c < cells; c += FB / 64) {
-        const double* src = a.partials + (int64_t)c * a.nblk;
-        double s = 0.0;
-        for (int b = lane; b < a.nblk; b += 64) s += src[b];
+    // one wave per cell (cell = blockIdx.x): lane l sums blocks l, l+64, ... in
+    // order, then a fixed xor-butterfly adds the 64 lane sums (same order every run)
+    const int c = blockIdx.x;
+    const int lane = threadIdx.x;
+    const double* src = a.partials + (int64_t)c * a.nblk;
+    double s = 0.0;
+    for (int b = lane; b < a.nblk; b += 64) s += src[b];
 #pragma unroll
-        for (int m = 32; m > 0; m >>= 1) s += __shfl_xor(s, m);
-        if (lane == 0) a.acc[c] = a.accumulate ? a.acc[c] + s : s;
-    }
-    __syncthreads();
+    for (int m = 32; m > 0; m >>= 1) s += __shfl_xor(s, m);
+    if (lane == 0) a.acc[c] = a.accumulate ? a.acc[c] + s : s;
+}
+
+__global__ __launch_bounds__(64) void k_vegas_update(VegasArgs a)
+{
+    // after the reduction: refine the grid (one lane per dimension) and advance
+    // the event counter of the random-number stream
     if (a.update_edges && threadIdx.x < a.d) {
         const int k = threadIdx.x;
         refine_dim(a.acc + 2 + k * a.nb, a.edges + k * (a.nb + 1), a.nb, a.alpha);
@@ -169,7 +170,10 @@ hipError_t launch_vegas(const VegasArgs& a, hipStream_t s)
     hipLaunchKernelGGL(k_vegas_accumulate, dim3(a.nblk), dim3(VB), 0, s, a);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
-    hipLaunchKernelGGL(k_vegas_finalize, dim3(1), dim3(FB), 0, s, a);
+    hipLaunchKernelGGL(k_vegas_reduce, dim3(2 + a.d * a.nb), dim3(64), 0, s, a);
+    err = hipGetLastError();
+    if (err != hipSuccess || !(a.update_edges || a.rng_counter)) return err;
+    hipLaunchKernelGGL(k_vegas_update, dim3(1), dim3(64), 0, s, a);
     return hipGetLastError();
 }
 

@@ -250,6 +250,7 @@ class Recursion:
         self.q, self.qmoms = q, qmoms
         self.qsum_memo = {}
         self.qmemo = {(): ub}
+        self.psimemo = {}
 
     def QP(self, rho):
         key = tuple(sorted(rho))
@@ -285,31 +286,40 @@ class Recursion:
             [(cneg(q, psi[0]), Jtb), (psi[1], Jp)],
         ]
 
-    def Q(self, prefix):
-        """Row spinor ubar Jslash .. S(q) after the gluons of ``prefix`` (propagator included)."""
-        if prefix in self.qmemo:
-            return self.qmemo[prefix]
+    def psi(self, prefix):
+        """Row spinor ubar Jslash .. Jslash(last block of prefix), before the propagator of prefix."""
+        if prefix in self.psimemo:
+            return self.psimemo[prefix]
         q = self.q
         terms = [[] for _ in range(4)]
         for s in range(len(prefix)):
             rows = self.slash_row(self.Q(prefix[:s]), self.QJ(prefix[s:]))
             for c in range(4):
                 terms[c] += rows[c]
-        psi = [cmat(q, csum(q, terms[c])) for c in range(4)]
+        self.psimemo[prefix] = [cmat(q, csum(q, terms[c])) for c in range(4)]
+        return self.psimemo[prefix]
+
+    def propagator(self, b, Pp, iq):
+        """(q+, q-, qt, qtb) and m, each times 1/(q^2 - m^2), of q = p_t - Pp, emitted into ``b``."""
+        qE = b.sub(S(name='PT[0]'), Pp.E)
+        qx = b.sub(S(name='PT[1]'), Pp.x)
+        qy = b.sub(S(name='PT[2]'), Pp.y)
+        qz = b.sub(S(name='PT[3]'), Pp.z)
+        qp = b.mul(b.add(qE, qz), iq)
+        qm = b.mul(b.sub(qE, qz), iq)
+        qxs = b.mul(qx, iq)
+        qys = b.mul(qy, iq)
+        ms = b.mul(S(name='MT'), iq)
+        return [C(qp), C(qm), C(qxs, qys), C(qxs, b.neg(qys))], ms
+
+    def Q(self, prefix):
+        """Row spinor ubar Jslash .. S(q) after the gluons of ``prefix`` (propagator included)."""
+        if prefix in self.qmemo:
+            return self.qmemo[prefix]
+        q = self.q
+        psi = self.psi(prefix)
         # propagator: (psi qslash + m psi)/(q^2 - m^2), q = p_t - P(prefix)
-        n = _sname(sorted(prefix))
-        iq = S(name=f'iq{n}')
-        Pp = self.QP(prefix)
-        qE = q.sub(S(name='PT[0]'), Pp.E)
-        qx = q.sub(S(name='PT[1]'), Pp.x)
-        qy = q.sub(S(name='PT[2]'), Pp.y)
-        qz = q.sub(S(name='PT[3]'), Pp.z)
-        qp = q.mul(q.add(qE, qz), iq)
-        qm = q.mul(q.sub(qE, qz), iq)
-        qxs = q.mul(qx, iq)
-        qys = q.mul(qy, iq)
-        ms = q.mul(S(name='MT'), iq)
-        qlc = [C(qp), C(qm), C(qxs, qys), C(qxs, q.neg(qys))]
+        qlc, ms = self.propagator(q, self.QP(prefix), S(name=f'iq{_sname(sorted(prefix))}'))
         rows = self.slash_row(psi, qlc)
         out_ = []
         for c in range(4):
