@@ -67,13 +67,15 @@ def measured_traffic(precision_name):
     return float(v) if v else None
 
 
-def flops_per_event(proc):
-    """Generated-code flop count per event (recursion + colour sum, FMA = 2)."""
+def flops_per_event(proc, fp64):
+    """Flops per event of the form the FP64 or the FP32 kernels execute (generated-code
+    count of the recursion and the colour form, FMA = 2)."""
+    import ast
     path = os.path.join(ROOT, 'paper_2211_14056_amd', 'csrc', 'generated', 'flops.txt')
     for line in open(path):
         name, rest = line.split(' ', 1)
         if name == proc:
-            return eval(rest, {})['per_event']       # the file holds a dict literal we wrote
+            return ast.literal_eval(rest)['per_event_f64' if fp64 else 'per_event_f32']
     raise KeyError(proc)
 
 
@@ -187,11 +189,12 @@ def main():
     rel = ((head['me'].double() - ref['me']) / ref['me']).abs()[ok]
     q = torch.quantile(rel[:100000].float(), torch.tensor([0.5, 0.99], device=rel.device)).tolist()
     rel_stats = dict(median=q[0], p99=q[1], max=float(rel.max()), events=int(ok.sum()))
-    fl = flops_per_event(PROC)
+    fl = flops_per_event(PROC, prec == mf.MF_FP64)
+    fl64 = flops_per_event(PROC, True)
     ev_s = args.steps * BATCH / head['seconds']
     ev_s64 = args.steps * BATCH / ref['seconds']
     me_ach = fl * BATCH / (head['me_ms'] * 1e-3)
-    me_ach64 = fl * BATCH / (ref['me_ms'] * 1e-3)
+    me_ach64 = fl64 * BATCH / (ref['me_ms'] * 1e-3)
     dt = 'f32'
     pname = [k for k, v in mf.PRECISION.items() if v == prec][0]
     out = {
@@ -216,7 +219,7 @@ def main():
                  'me_events_per_s': BATCH / (ref['me_ms'] * 1e-3),
                  'roofline': {'bound': 'alu', 'achieved': me_ach64 / 1e12, 'peak': PEAK['f64'] / 1e12,
                               'unit': 'TFLOP/s', 'frac': me_ach64 / PEAK['f64'],
-                              'traffic': measured_traffic('fp64')}},
+                              'traffic': measured_traffic('fp64'), 'flops_per_event': fl64}},
         'roofline': {'bound': 'alu', 'achieved': me_ach / 1e12, 'peak': PEAK['f32'] / 1e12, 'unit': 'TFLOP/s',
                      'frac': me_ach / PEAK['f32'], 'traffic': measured_traffic(pname),
                      'kernel': 'matrix element', 'flops_per_event': fl},

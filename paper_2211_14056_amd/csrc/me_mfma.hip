@@ -67,16 +67,25 @@ __global__ __launch_bounds__(256) void k_me_mfma(const double* __restrict__ p, i
         sink.init(me_gg_ttg_cnum);
         me_gg_ttg_amps<float>(pe, mt, sink);
         if (e0 < n) out[e0] = (float)((double)sink.acc * coupling * me_gg_ttg_norm_noalpha());
-    } else {
-        // one wave per block: multi-gluon currents parked in this wave's LDS columns
-        __shared__ float smem[me_gg_ttgg_amps_slots * 64];
-        double pe[6][4];
-        load_event<6>(p, n, e, pe);
-        MfmaColour<24, MODE> sink;
-        sink.init(me_gg_ttgg_cnum);
-        me_gg_ttgg_amps<float>(pe, mt, sink, smem + (threadIdx.x & 63));
-        if (e0 < n) out[e0] = (float)((double)sink.acc * coupling * me_gg_ttgg_norm_noalpha());
     }
+}
+
+// gg -> ttbar gg: one wave per block, its multi-gluon currents parked in the
+// wave's LDS columns (the launch bound of one wave lets the compiler plan the
+// register file for exactly one wave per SIMD)
+template <int MODE>
+__global__ __launch_bounds__(64) void k_me_mfma_ttgg(const double* __restrict__ p, int64_t n,
+                                                     float* __restrict__ out, double mt, double coupling)
+{
+    __shared__ float smem[me_gg_ttgg_amps_slots * 64];
+    const int64_t e0 = (int64_t)blockIdx.x * 64 + threadIdx.x;
+    const int64_t e = e0 < n ? e0 : n - 1;
+    double pe[6][4];
+    load_event<6>(p, n, e, pe);
+    MfmaColour<24, MODE> sink;
+    sink.init(me_gg_ttgg_cnum);
+    me_gg_ttgg_amps<float>(pe, mt, sink, smem + threadIdx.x);
+    if (e0 < n) out[e0] = (float)((double)sink.acc * coupling * me_gg_ttgg_norm_noalpha());
 }
 
 template <int MODE>
@@ -89,7 +98,7 @@ hipError_t launch_mode(const MeJob& j, double mt, double coupling, int block, hi
     case GG_TTG: hipLaunchKernelGGL((k_me_mfma<GG_TTG, MODE>), dim3(grid), dim3(block), 0, s, j.p, j.n, out, mt, coupling); break;
     case GG_TTGG: {
         const unsigned g64 = (unsigned)((j.n + 63) / 64);
-        hipLaunchKernelGGL((k_me_mfma<GG_TTGG, MODE>), dim3(g64), dim3(64), 0, s, j.p, j.n, out, mt, coupling);
+        hipLaunchKernelGGL((k_me_mfma_ttgg<MODE>), dim3(g64), dim3(64), 0, s, j.p, j.n, out, mt, coupling);
         break;
     }
     default: return hipErrorInvalidValue;

@@ -393,6 +393,23 @@ def test_vegas_gg_tt_closed_form(h):
     assert abs(I - ref) < 3 * sig
 
 
+def test_vegas_pull_distribution(h):
+    """Vegas on the GPU over 20 seeds: the pulls (I - closed form)/sigma of sigma(ee->mumu) and
+    sigma_hat(gg->ttbar) are consistent with N(0, 1) (mean and spread within their 3-sigma sampling
+    ranges for 20 draws), so the quoted errors are the statistical ones."""
+    ref = {'ee_mumu': closed_forms.ee_mumu_sigma(PEE['sqrt_s'] ** 2, PEE['alpha']) * closed_forms.GEV2_TO_PB,
+           'gg_tt': closed_forms.gg_tt_sigma(P['sqrt_s'] ** 2, P['m_t'], P['alpha_s']) * closed_forms.GEV2_TO_PB}
+    for proc, n, iters in (('ee_mumu', 20_000, 4), ('gg_tt', 50_000, 4)):
+        pulls = []
+        for seed in range(1, 21):
+            (I, sig, chi2), _, _, _ = _gpu_vegas(h, proc, n, iters, seed=100 + seed)
+            pulls.append((I - ref[proc]) / sig)
+        pulls = np.array(pulls)
+        say('vegas pulls', proc, 'mean', pulls.mean(), 'std', pulls.std(ddof=1))
+        assert abs(pulls.mean()) < 3 / math.sqrt(20)
+        assert 0.5 < pulls.std(ddof=1) < 1.5
+
+
 # ------------------------------------------------------------------ a9: derivative
 def _vjp_gpu(h, proc, x, gbar, precision, edges=None):
     pid = mf.PROCESS[proc]
