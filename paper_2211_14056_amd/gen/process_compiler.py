@@ -249,13 +249,19 @@ class Recursion:
         """Quark-line block ``q``, the gluon momenta as seen there, and the row spinor ubar.
         share_products: form each product Q(prefix) Jslash(block) that the quark lines of
         ``orderings`` use more than once (a block and its reflection give the same product up
-        to sign) once, and add it where it is used."""
+        to sign) once, and add it where it is used.  Left out: ubar Jslash(sigma) of a whole
+        ordering, whose two uses (sigma and its reverse) are in the groups of different first
+        gluons, so the shared value would stay live across most of the quark line."""
         self.q, self.qmoms = q, qmoms
         self.qsum_memo = {}
         self.qmemo = {(): ub}
         self.psimemo = {}
         self.pmemo = {}
-        self.puses = self._count_products(orderings) if share_products else {}
+        self.puses = {}
+        if share_products:
+            k = max((len(o) for o in orderings), default=0)
+            self.puses = {key: v for key, v in self._count_products(orderings).items()
+                          if not (key[0] == () and len(key[1]) == k)}
 
     def _count_products(self, orderings):
         """Occurrences of each product Q(prefix) Jslash(block), block up to reflection, on the
@@ -640,7 +646,7 @@ LDS_F64 = 72
 # The four-lanes-per-event FP64 kernel runs two waves per compute unit: 80 KB of
 # LDS per wave, 160 doubles per lane.
 LDS_QUAD_F64 = 152
-# Shared quark-line products (Recursion.start_quark_line): 17% fewer flops for
+# Shared quark-line products (Recursion.start_quark_line): 13% fewer flops for
 # gg -> ttbar gg.  The FP32 kernels run faster with them.  The FP64 kernel, whose
 # working set already spills, runs slower (the shared values add to the spill), so it
 # keeps the plain form.

@@ -228,6 +228,25 @@ def test_me_full_size_sampled(h, proc, n):
             assert rel[ok].max() < 1e-3
 
 
+def test_me_fp32_forms_vs_fp64_every_event_full_size(h):
+    """Every event of a 10^6-event gg -> ttbar gg batch (the benchmark launch): each FP32 form
+    (VALU colour, FP32-MFMA colour, BF16x3-MFMA colour) against the FP64 kernel, which the
+    tests above pin to the oracle.  Bars on the events passing the cuts: median 1e-5, max 1e-3.
+    Checking all events, not a sample, would expose a kernel build that is wrong on a subset."""
+    n = 1_000_000
+    say('me fp32 forms vs fp64, every event', n)
+    ev = gpu_events(h, 'gg_ttgg', n, seed=4)
+    ref = mf.matrix_element(h, mf.MF_GG_TTGG, ev['p'], mf.MF_FP64)
+    ok = ev['pass_'].bool()
+    for prec in (mf.MF_FP32, mf.MF_FP32_MFMA_F32, mf.MF_FP32_MFMA_BF16):
+        me = mf.matrix_element(h, mf.MF_GG_TTGG, ev['p'], prec)
+        torch.cuda.synchronize()
+        assert bool(torch.isfinite(me).all())
+        rel = ((me.double() - ref) / ref).abs()[ok]
+        say('  precision', prec, 'median', float(rel.median()), 'max', float(rel.max()))
+        assert float(rel.median()) < 1e-5 and float(rel.max()) < 1e-3
+
+
 def test_me_lorentz_invariance_fp64(h):
     n = 512
     say('lorentz gg_ttgg', n)
