@@ -9,7 +9,11 @@ path is measured on the same batches and reported beside it, with the
 per-event relative difference of the FP32 result from the FP64 one (the FP64
 path matches the FP64 CPU oracle to 1e-12 in the parity tests).
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp32_mfma_f32]
+Beside the headline the JSON line carries `extras`: the derivative (VJP) on the
+gg -> ttbar g configuration (4e6 events, FP32 and FP64) and the 64-request mixed
+batch, one persistent launch against one launch per request.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp32_mfma_f32] [--no-extras]
 """
 import argparse
 import json
@@ -122,6 +126,65 @@ def run_path(mf, h, prm, precision, steps, warmup, seed):
     return dict(seconds=t1 - t0, me_ms=float(np.mean(me_ms)), me=me, pas=pas, acc=acc)
 
 
+def _best_ms(fn, reps=3):
+    """Best of `reps` timed calls (HIP events on the current stream) after one warm-up call."""
+    fn()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    best = float('inf')
+    for _ in range(reps):
+        a.record()
+        fn()
+        b.record()
+        b.synchronize()
+        best = min(best, a.elapsed_time(b))
+    return best
+
+
+def extras(mf, h, prm, seed):
+    """The other rows of the path, timed beside the headline: the derivative on the
+    gg -> ttbar g configuration (4e6 events) and the 64-request mixed batch in one
+    persistent launch against one launch per request."""
+    from paper_2211_14056_amd.workloads import mixed_batch
+    dev = torch.device('cuda', 0)
+    f64 = dict(dtype=torch.float64, device=dev)
+    out = {}
+    pid, n = mf.MF_GG_TTG, 4_000_000
+    d = mf.mf_process_dims(pid)
+    x = torch.empty(d, n, **f64)
+    mf.mf_phase_space(h, pid, prm, n, seed=seed, x_out=x)
+    gx, gth = torch.empty(d, n, **f64), torch.empty(n, 2, **f64)
+    gb = torch.ones(n, **f64)
+    vjp = {}
+    for name, prec in (('fp32', mf.MF_FP32), ('fp64', mf.MF_FP64)):
+        me = torch.empty(n, dtype=torch.float32 if prec == mf.MF_FP32 else torch.float64, device=dev)
+        req = mf.make_request(pid, None, me, x=x, grad_me=gb, grad_x=gx, grad_theta=gth, n=n)
+        fwd = mf.make_request(pid, mf.mf_phase_space(h, pid, prm, n, seed=seed)['p'], me)
+        t = _best_ms(lambda: mf.mf_matrix_element_vjp(h, [req], prec, prm))
+        tf = _best_ms(lambda: mf.mf_matrix_element(h, [fwd], prec, prm))
+        vjp[name] = {'ms': t, 'events_per_s': n / t * 1e3, 'forward_ms': tf, 'vjp_over_forward': t / tf}
+    out['vjp_gg_ttg'] = {'events': n, 'inputs_per_event': d + 2, **vjp}
+    del x, gx, gth, gb
+    spec = mixed_batch(64, seed=5)
+    reqs, keep = [], []
+    prec = mf.MF_FP32_MFMA_BF16
+    for i, (proc, m) in enumerate(spec):
+        q = mf.PROCESS[proc]
+        p = mf.mf_phase_space(h, q, prm, m, seed=seed + 100 + i)['p']
+        o = torch.empty(m, dtype=torch.float32, device=dev)
+        keep += [p, o]
+        reqs.append(mf.make_request(q, p, o))
+    total = sum(m for _, m in spec)
+    h.set_launch(batch_persistent=1)
+    tp = _best_ms(lambda: mf.mf_matrix_element(h, reqs, prec, prm))
+    h.set_launch(batch_persistent=0)
+    ts = _best_ms(lambda: mf.mf_matrix_element(h, reqs, prec, prm))
+    h.set_launch(batch_persistent=1)
+    out['mixed_batch'] = {'requests': len(spec), 'events': total, 'precision': 'fp32_mfma_bf16',
+                          'persistent_ms': tp, 'per_request_ms': ts, 'events_per_s': total / tp * 1e3}
+    return out
+
+
 def cpu_baseline(seed, budget_s=45.0):
     """The FP64 oracle (colour-ordered mode) on the host cores, bounded sample."""
     from oracle import integrand, philox, processes, vegas as ovegas
@@ -155,6 +218,7 @@ def main():
     ap.add_argument('--warmup', type=int, default=2)
     ap.add_argument('--precision', default='auto')
     ap.add_argument('--no-cpu-baseline', action='store_true')
+    ap.add_argument('--no-extras', action='store_true', help='skip the derivative and mixed-batch timings')
     ap.add_argument('--seed', type=int, default=4)
     ap.add_argument('--copy-calibration', action='store_true',
                     help=f'also run one {COPY_BYTES >> 20} MiB device-to-device copy (counter calibration)')
@@ -224,6 +288,8 @@ def main():
                      'frac': me_ach / PEAK['f32'], 'traffic': measured_traffic(pname),
                      'kernel': 'matrix element', 'flops_per_event': fl},
     }
+    if not args.no_extras:
+        out['extras'] = extras(mf, h, prm, args.seed)
     if not args.no_cpu_baseline:
         out['cpu_baseline'] = cpu_baseline(args.seed)
     print(json.dumps(out))

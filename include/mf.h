@@ -114,10 +114,12 @@ int mf_process_dims(int proc);
  *     lanes per event (colour orderings split by first gluon, gluon currents
  *     shared within the quad), any other value = one lane per event (default).
  *     proc < 0 leaves the per-process settings unchanged.
- *   batch_waves_per_cu > 0: grid of the persistent mixed-batch launch
- *     (one-wave blocks per compute unit); <= 0 leaves it unchanged.
- *   batch_persistent: 1 = several requests in one call share one persistent
- *     launch (default), 0 = one launch per request, < 0 = unchanged.
+ *   batch_waves_per_cu >= 0: one-wave blocks per compute unit in each
+ *     persistent launch (0, the default: as many as the process's kernel fits);
+ *     < 0 leaves it unchanged.
+ *   batch_persistent: 1 = the requests of a call are served by persistent
+ *     launches, one per gg process class, each pulling 64-event tiles from a
+ *     queue (default); 0 = one launch per request; < 0 = unchanged.
  * Errors: MF_ERR_INVALID_ARG for out-of-range values. */
 mf_status mf_set_launch(mf_handle h, int proc, int precision, int block, int batch_waves_per_cu,
                         int batch_persistent);

@@ -150,7 +150,7 @@ class Handle:
         except Exception:
             pass
 
-    def set_launch(self, proc=-1, precision=0, block=0, batch_waves_per_cu=0, batch_persistent=-1):
+    def set_launch(self, proc=-1, precision=0, block=0, batch_waves_per_cu=-1, batch_persistent=-1):
         """mf_set_launch: per-(process, precision) block size and persistent-batch grid."""
         _check(lib().mf_set_launch(self.h, proc, precision, block, batch_waves_per_cu, batch_persistent))
 

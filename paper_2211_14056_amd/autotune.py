@@ -5,7 +5,8 @@ the time of a fixed workload a lot, with a plateau of good choices (sect. 3,
 Fig. 3).  Here the same question is answered by measurement on the device at
 hand: for each (process, precision) the single-request matrix-element launch
 is timed for every candidate block size, and the persistent mixed-batch
-launch for every candidate grid (one-wave workgroups per compute unit); the
+launches for every candidate grid (one-wave workgroups per compute unit, 0 =
+as many as fit) against one launch per request; the
 fastest is installed in the handle (mf_set_launch) and cached in a JSON file
 keyed by (GPU architecture, process, precision, batch-size bucket).
 
@@ -22,7 +23,7 @@ import torch
 from . import (MF_FP64, PROCESS, make_request, mf_matrix_element, mf_phase_space, mf_process_legs, params)
 
 BLOCKS = (64, 128, 192, 256)
-WAVES_PER_CU = (1, 2, 3, 4)
+WAVES_PER_CU = (0, 1, 2, 4)     # 0 = as many as fit
 
 
 def cache_path():

@@ -62,8 +62,12 @@ struct BatchReq {
     int64_t n;
     const double* p;
     void* out;
-    int64_t tile_begin;     // first 64-event tile of this request
+    int64_t tile_begin;     // first tile of this request (64 * batch_chunk(proc) events per tile)
 };
+
+// 64-event waves per tile of the persistent launch: cheap processes take several
+// per queue pop, so the queue's atomic is not on the critical path
+constexpr int batch_chunk(int proc) { return proc == GG_TT ? 16 : proc == GG_TTG ? 4 : 1; }
 
 struct BatchArgs {
     BatchReq req[MAX_BATCH];
@@ -74,9 +78,10 @@ struct BatchArgs {
     double coupling[4];     // per process: alpha (e+e-) or (4 pi alpha_s)^k
 };
 
-// One persistent launch over a mixed batch; precision as for
-// launch_matrix_element (gg processes only); grid = number of one-wave blocks.
-hipError_t launch_batch(const BatchArgs& a, int precision, int grid, hipStream_t s);
+// One persistent launch over requests of one gg process; precision as for
+// launch_matrix_element; waves_per_cu one-wave blocks per compute unit
+// (<= 0: as many as fit).
+hipError_t launch_batch(const BatchArgs& a, int precision, int waves_per_cu, int n_cu, hipStream_t s);
 
 struct VjpJob {
     int proc;

@@ -4,6 +4,6 @@
 
 namespace mf {
 
-template hipError_t launch_batch_one<double, 0>(const BatchArgs&, int, hipStream_t);
+template hipError_t launch_batch_one<double, 0>(const BatchArgs&, int, int, hipStream_t);
 
 }  // namespace mf

@@ -4,7 +4,7 @@
 
 namespace mf {
 
-template hipError_t launch_batch_one<float, 1>(const BatchArgs&, int, hipStream_t);
-template hipError_t launch_batch_one<float, 2>(const BatchArgs&, int, hipStream_t);
+template hipError_t launch_batch_one<float, 1>(const BatchArgs&, int, int, hipStream_t);
+template hipError_t launch_batch_one<float, 2>(const BatchArgs&, int, int, hipStream_t);
 
 }  // namespace mf

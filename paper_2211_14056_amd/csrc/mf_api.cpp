@@ -43,7 +43,7 @@ struct mf_handle_s {
     unsigned* tile_counter = nullptr;  // persistent-batch work queue
     // launch configuration (set by mf_set_launch / the autotuner)
     int block[4][4];                   // [process][precision] threads per block, 0 = default
-    int batch_waves_per_cu = 4;        // persistent grid = waves_per_cu * n_cu one-wave blocks
+    int batch_waves_per_cu = 0;        // persistent grid = waves_per_cu * n_cu one-wave blocks (0: as many as fit)
     int batch_persistent = 1;          // 0 = one launch per request instead
 };
 
@@ -153,9 +153,9 @@ mf_status mf_set_launch(mf_handle h, int proc, int precision, int block, int bat
             return fail(MF_ERR_INVALID_ARG, "mf_set_launch: block must be 64, 128, 192 or 256 (0 = default)");
         h->block[proc][precision] = block;
     }
-    if (batch_waves_per_cu > 0) {
+    if (batch_waves_per_cu >= 0) {
         if (batch_waves_per_cu > 16)
-            return fail(MF_ERR_INVALID_ARG, "mf_set_launch: batch_waves_per_cu must be in [1, 16]");
+            return fail(MF_ERR_INVALID_ARG, "mf_set_launch: batch_waves_per_cu must be in [0, 16]");
         h->batch_waves_per_cu = batch_waves_per_cu;
     }
     if (batch_persistent >= 0) h->batch_persistent = batch_persistent ? 1 : 0;
@@ -250,7 +250,7 @@ mf_status mf_matrix_element(mf_handle h, const mf_request* reqs, int n_reqs, int
     if (st != MF_OK) return st;
     DeviceGuard g(h->device);
     hipStream_t st_ = static_cast<hipStream_t>(stream);
-    // gg requests of a multi-request call go to one persistent launch
+    // gg requests of a multi-request call go to persistent launches, one per process class
     int order[3] = {MF_GG_TTGG, MF_GG_TTG, MF_GG_TT};   // most expensive first
     bool batched[4096] = {false};
     if (n_reqs > 1 && n_reqs <= 4096 && h->batch_persistent) {
@@ -264,14 +264,13 @@ mf_status mf_matrix_element(mf_handle h, const mf_request* reqs, int n_reqs, int
         }
         auto flush = [&]() -> mf_status {
             if (a.nreq == 0) return MF_OK;
-            const int grid = h->batch_waves_per_cu * h->n_cu;
-            hipError_t e = mf::launch_batch(a, precision, grid, st_);
+            hipError_t e = mf::launch_batch(a, precision, h->batch_waves_per_cu, h->n_cu, st_);
             if (e != hipSuccess) return hip_fail(e, "mf_matrix_element persistent launch");
             a.nreq = 0;
             a.ntiles = 0;
             return MF_OK;
         };
-        for (int proc : order)
+        for (int proc : order) {
             for (int i = 0; i < n_reqs; ++i) {
                 const mf_request& r = reqs[i];
                 if (r.proc != proc || r.n == 0) continue;
@@ -285,11 +284,13 @@ mf_status mf_matrix_element(mf_handle h, const mf_request* reqs, int n_reqs, int
                 q.p = r.p;
                 q.out = r.me_out;
                 q.tile_begin = a.ntiles;
-                a.ntiles += (r.n + 63) / 64;
+                const int64_t tile = 64 * mf::batch_chunk(r.proc);
+                a.ntiles += (r.n + tile - 1) / tile;
                 batched[i] = true;
             }
-        mf_status s2 = flush();
-        if (s2 != MF_OK) return s2;
+            mf_status s1 = flush();     // one launch per process class
+            if (s1 != MF_OK) return s1;
+        }
     }
     for (int i = 0; i < n_reqs; ++i) {
         if (reqs[i].n == 0 || (i < 4096 && batched[i])) continue;

@@ -610,11 +610,18 @@ def test_mixed_batch_full_size_one_launch(h):
     spec = mixed_batch(64, seed=5)
     say('mixed batch full size', sum(n for _, n in spec), 'events')
     reqs, outs, evs = _mixed_requests(h, spec, mf.MF_FP32_MFMA_BF16)
+    h.set_launch(batch_persistent=0)
+    mf.mf_matrix_element(h, reqs, mf.MF_FP32_MFMA_BF16, mf.params())
+    torch.cuda.synchronize()
+    sep = [o.clone() for o in outs]
+    h.set_launch(batch_persistent=1)
     mf.mf_matrix_element(h, reqs, mf.MF_FP32_MFMA_BF16, mf.params())
     torch.cuda.synchronize()
     rng = np.random.default_rng(3)
-    for (proc, n), out, ev in zip(spec, outs, evs):
+    for (proc, n), out, ev, ref in zip(spec, outs, evs, sep):
         assert bool(torch.isfinite(out).all())
+        # every event equals the single-request launch (same generated body, other kernel)
+        assert float(((out.double() - ref.double()).abs() / ref.double().abs()).max()) <= 1e-6
     for i in rng.choice(len(spec), 6, replace=False):
         proc, n = spec[i]
         idx = torch.tensor(rng.choice(n, min(n, 4), replace=False), device='cuda')
