@@ -411,7 +411,7 @@ def _sname(sub):
 
 
 def emit_qcd(proc, with_colour=True, opaque_inputs=True, group_barriers=True, lds_budget=0, constants=True,
-             barrier_every=0, stream=False, share_products=False):
+             stream=False, share_products=False):
     """Return (source text, flop counts) of the device function for ``proc``.
 
     opaque_inputs: re-declare the momenta as opaque at the top of each helicity
@@ -425,8 +425,6 @@ def emit_qcd(proc, with_colour=True, opaque_inputs=True, group_barriers=True, ld
       slots when computed and re-read at each use on the quark line, so they do
       not occupy registers across the top-helicity loop.  The emitted body then
       takes an LDS pointer (this lane's column, stride 64) as extra argument.
-    barrier_every: if > 0, a scheduling barrier after every that many emitted
-      statements, which pins the instruction order close to the emission order.
     stream: fold each vertex split of a gluon current into running sums as soon
       as its coefficients are formed (fewer values live at once; same arithmetic).
     share_products: form a quark-line product Q(prefix) Jslash(block) used by several
@@ -570,17 +568,6 @@ def emit_qcd(proc, with_colour=True, opaque_inputs=True, group_barriers=True, ld
     colour_flops = cs.flops
 
     # ---------------- emit ----------------
-    def fence(lines):
-        if not barrier_every:
-            return lines
-        res = []
-        for i, l in enumerate(lines):
-            res.append(l)
-            if (i + 1) % barrier_every == 0:
-                res.append('__builtin_amdgcn_sched_barrier(0);')
-        return res
-    gluon_lines = fence(gluon_lines)
-    q.lines = fence(q.lines)
     body = []
     opq = []
     if opaque_inputs:
