@@ -21,7 +21,8 @@
  *  - Layouts are structure-of-arrays with the event index fastest.
  *    Momenta: p[leg][component][event], component = (E, px, py, pz), legs in
  *    the order of the process (incoming first), FP64.
- *  - n = 0 is a valid no-op (returns MF_OK) except where stated.
+ *  - n = 0 is a valid no-op (returns MF_OK) except where stated; n above 2^36
+ *    events per call or request is rejected (MF_ERR_INVALID_ARG).
  *  - Numerical trouble is not an error: NaN inputs give NaN outputs; an
  *    event whose massive phase-space rescaling does not converge gets
  *    weight 0 and is counted (mf_failures).

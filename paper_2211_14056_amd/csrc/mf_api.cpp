@@ -32,6 +32,9 @@ mf_status hip_fail(hipError_t e, const char* where)
 
 bool valid_proc(int p) { return p >= MF_EE_MUMU && p <= MF_GG_TTGG; }
 
+// largest batch a call accepts: keeps every launch grid within 32 bits
+constexpr int64_t kMaxEvents = int64_t(1) << 36;
+
 }  // namespace
 
 struct mf_handle_s {
@@ -121,6 +124,7 @@ mf_status mf_create(int device, mf_handle* out)
     e = hipMemset(h->fail_dev, 0, sizeof(unsigned long long));
     if (e != hipSuccess) {
         hipFree(h->fail_dev);
+        hipFree(h->tile_counter);
         delete h;
         return hip_fail(e, "mf_create: hipMemset");
     }
@@ -184,7 +188,8 @@ mf_status mf_phase_space(mf_handle h, int proc, const mf_params* prm, int64_t n,
     if (!h) return fail(MF_ERR_INVALID_ARG, "mf_phase_space: NULL handle");
     if (!valid_proc(proc)) return fail(MF_ERR_INVALID_ARG, "mf_phase_space: unknown process %d", proc);
     if (!prm) return fail(MF_ERR_INVALID_ARG, "mf_phase_space: NULL params");
-    if (n < 0) return fail(MF_ERR_INVALID_ARG, "mf_phase_space: n = %lld < 0", (long long)n);
+    if (n < 0 || n > kMaxEvents)
+        return fail(MF_ERR_INVALID_ARG, "mf_phase_space: n = %lld outside [0, 2^36]", (long long)n);
     if (n == 0) return MF_OK;
     if (!p || !w) return fail(MF_ERR_INVALID_ARG, "mf_phase_space: NULL p or w");
     if ((edges || bin_idx) && (nb < 2 || nb > 64))
@@ -231,7 +236,7 @@ static mf_status check_requests(const char* who, const mf_request* reqs, int n_r
     for (int i = 0; i < n_reqs; ++i) {
         const mf_request& r = reqs[i];
         if (!valid_proc(r.proc)) return fail(MF_ERR_INVALID_ARG, "%s: request %d: unknown process %d", who, i, r.proc);
-        if (r.n < 0) return fail(MF_ERR_INVALID_ARG, "%s: request %d: n < 0", who, i);
+        if (r.n < 0 || r.n > kMaxEvents) return fail(MF_ERR_INVALID_ARG, "%s: request %d: n outside [0, 2^36]", who, i);
         if (r.n == 0) continue;
         if (!r.p && !vjp) return fail(MF_ERR_INVALID_ARG, "%s: request %d: NULL p", who, i);
         if (!vjp && !r.me_out) return fail(MF_ERR_INVALID_ARG, "%s: request %d: NULL me_out", who, i);
@@ -357,7 +362,7 @@ mf_status mf_vegas_refine(mf_handle h, const mf_params* prm, int64_t n, int d, i
     if (!prm) return fail(MF_ERR_INVALID_ARG, "mf_vegas_refine: NULL params");
     if (d < 1 || d > 8) return fail(MF_ERR_INVALID_ARG, "mf_vegas_refine: d = %d outside [1, 8]", d);
     if (nb < 2 || nb > 64) return fail(MF_ERR_INVALID_ARG, "mf_vegas_refine: nb = %d outside [2, 64]", nb);
-    if (n < 0) return fail(MF_ERR_INVALID_ARG, "mf_vegas_refine: n < 0");
+    if (n < 0 || n > kMaxEvents) return fail(MF_ERR_INVALID_ARG, "mf_vegas_refine: n outside [0, 2^36]");
     if (!acc || !edges) return fail(MF_ERR_INVALID_ARG, "mf_vegas_refine: NULL acc or edges");
     if (n > 0 && (!w || !me || !bin_idx))
         return fail(MF_ERR_INVALID_ARG, "mf_vegas_refine: NULL w, me or bin_idx");

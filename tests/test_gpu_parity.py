@@ -568,6 +568,17 @@ def test_precision_errors(h):
     assert ei.value.status == -1
 
 
+def test_oversized_request_rejected_before_launch(h):
+    """A request above 2^36 events is refused by the argument check (nothing is launched: the
+    buffers named here are far smaller than the request)."""
+    import ctypes
+    small = torch.empty(64, dtype=torch.float64, device='cuda')
+    r = mf.mf_request(mf.MF_GG_TT, 0, (1 << 36) + 1, small.data_ptr(), small.data_ptr(), None, None, None, None)
+    arr = (mf.mf_request * 1)(r)
+    st = mf.lib().mf_matrix_element(h.h, arr, 1, mf.MF_FP64, ctypes.byref(mf.params()), None)
+    assert st == -1 and b'2^36' in mf.lib().mf_last_error()
+
+
 # ------------------------------------------------------------------ a10: persistent batch, graphs, tuning
 def _mixed_requests(h, spec, precision, seed0=200):
     reqs, outs, evs = [], [], []
