@@ -145,6 +145,61 @@ def test_lorentz_invariance(proc, N):
     assert ((a / b - 1).abs()).max() < 1e-12
 
 
+@pytest.mark.parametrize('proc,N', [('gg_tt', 6), ('gg_ttg', 4), ('gg_ttgg', 2)])
+def test_parke_taylor_mhv_massless_limit(proc, N):
+    """Absolute normalisation of the colour-ordered partial amplitudes, k = 2, 3, 4 gluons.
+
+    At m_t = 0 the quark-gluon MHV amplitudes have the closed Parke-Taylor form (Parke and
+    Taylor 1986; Berends and Giele 1988; reviewed in Mangano and Parke, Phys. Rept. 200 (1991)).
+    All momenta are taken outgoing, so the helicity of an incoming gluon is flipped.  For a
+    configuration with antiquark helicity h and exactly one gluon j of the same helicity h
+    (MHV for h = -, its conjugate for h = +):
+        |A(sigma)|^2 = 2^k g^(2k) s(tbar, j)^3 s(t, j) / [s(t, g_sigma1) s(g_sigma1, g_sigma2) ... s(g_sigmak, tbar) s(tbar, t)]
+    with s(a, b) = |(p_a + p_b)^2|.  The factor 2^k comes from the colour basis: t^a = lambda^a/2
+    here, against lambda^a/sqrt(2) in the usual statement of the formula.  Equal quark helicities
+    and gluons all of the opposite helicity to the antiquark give zero.  This pins every vertex
+    normalisation and the overall factors of tt g and tt gg, which the other pins fix only relatively."""
+    P0 = dict(P)
+    P0['m_t'] = 0.0
+    p = events(proc, N, 31, params=P0)
+    n_ext = p.shape[1]
+    k = n_ext - 2
+    gl = [0, 1] + list(range(4, n_ext))
+    po = p.clone()
+    po[:, :2] = -p[:, :2]                       # all momenta outgoing
+
+    def sij(a, b):
+        x = po[:, a] + po[:, b]
+        return (x[:, 0] ** 2 - x[:, 1] ** 2 - x[:, 2] ** 2 - x[:, 3] ** 2).abs()
+
+    g2 = 4 * math.pi * P0['alpha_s']
+    orders = colour.orderings(k)
+    scale = max(me_ordered.partial_amplitudes(p, h, P0).abs().max() for h in processes.helicities(proc))
+    n_mhv = 0
+    for hel in processes.helicities(proc):
+        A = me_ordered.partial_amplitudes(p, hel, P0)
+        h = list(hel)
+        h[0], h[1] = -h[0], -h[1]
+        ht, htb = h[2], h[3]
+        gh = [h[l] for l in gl]
+        if ht == htb or gh.count(htb) == 0:
+            assert A.abs().max() < 1e-13 * scale, hel
+            continue
+        if gh.count(htb) != 1:
+            continue                             # not MHV: no closed form
+        j = gl[gh.index(htb)]
+        num = sij(3, j) ** 3 * sij(2, j)
+        for si, sigma in enumerate(orders):
+            chain = [2] + [gl[i] for i in sigma] + [3]
+            den = torch.ones(N, dtype=torch.float64)
+            for a, b in zip(chain, chain[1:] + chain[:1]):
+                den = den * sij(a, b)
+            want = 2 ** k * g2 ** k * num / den
+            assert ((A[:, si].abs() ** 2 / want - 1).abs()).max() < 1e-10, (hel, sigma)
+            n_mhv += 1
+    assert n_mhv == 2 * k * len(orders)          # both quark helicity pairs, each gluon as j
+
+
 @pytest.mark.parametrize('proc,N', [('gg_tt', 30), ('gg_ttg', 10), ('gg_ttgg', 4)])
 def test_bose_symmetry(proc, N):
     p = events(proc, N, 8)
