@@ -151,6 +151,26 @@ def test_me_fp64_vs_oracle(h, proc):
     assert rel.max() < 1e-12
 
 
+@pytest.mark.parametrize('proc', ['gg_tt', 'gg_ttg', 'gg_ttgg'])
+def test_me_fp64_massless_limit_vs_oracle(h, proc):
+    """m_t = 0: the GPU kernels against the oracle in the limit where the oracle's partial
+    amplitudes are pinned to the Parke-Taylor form (massless spinors and propagators)."""
+    n = ME_N[proc] + 3
+    par = dict(P)
+    par['m_t'] = 0.0
+    prm = mf.params_from_dict(par)
+    pid = mf.PROCESS[proc]
+    say('me fp64 massless', proc, n)
+    ev = mf.mf_phase_space(h, pid, prm, n, seed=23)
+    me = mf.matrix_element(h, pid, ev['p'], mf.MF_FP64, prm)
+    torch.cuda.synchronize()
+    pt = torch.tensor(np.ascontiguousarray(np.transpose(ev['p'].cpu().numpy(), (2, 0, 1))), dtype=torch.float64)
+    ref = integrand.me(proc, pt, par).numpy()
+    rel = np.abs(me.cpu().numpy() / ref - 1)
+    say('  max rel', rel.max())
+    assert rel.max() < 1e-12
+
+
 @pytest.mark.parametrize('proc', PROCS)
 def test_me_fp32_vs_oracle(h, proc):
     n = ME_N[proc] + 3
