@@ -9,11 +9,17 @@ path is measured on the same batches and reported beside it, with the
 per-event relative difference of the FP32 result from the FP64 one (the FP64
 path matches the FP64 CPU oracle to 1e-12 in the parity tests).
 
+By default the batches are pipelined over two HIP streams: the phase space of
+batch i+1 runs beside the matrix element of batch i (`--streams 1` serialises
+them).  The matrix elements stay on one stream, one at a time, so the HIP events
+around each matrix-element launch time that kernel alone; the roofline figures
+come from those launch durations, the headline from the wall clock of the steps.
+
 Beside the headline the JSON line carries `extras`: the derivative (VJP) on the
 gg -> ttbar g configuration (4e6 events, FP32 and FP64) and the 64-request mixed
 batch, one persistent launch against one launch per request.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp32_mfma_f32] [--no-extras]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp32_mfma_f32] [--no-extras] [--streams 1|2]
 """
 import argparse
 import json
@@ -83,47 +89,110 @@ def flops_per_event(proc, fp64):
     raise KeyError(proc)
 
 
-def run_path(mf, h, prm, precision, steps, warmup, seed):
-    """Time `steps` batches of the full forward path; returns timings and last ME."""
+def enqueue_order(first, count, streams):
+    """[(op, batch)] in the order the batches first..first+count-1 are enqueued.
+
+    op 'ps' is the phase space of the batch, op 'rest' its matrix element and Vegas
+    call.  With two buffers the phase space of i+1 is enqueued before the rest of i,
+    except where i+1 opens a Vegas iteration: its phase space needs the grid that
+    batch i's refine writes, so it comes after that refine.  With one buffer it
+    always comes after the rest of i, which still reads the buffer."""
+    order = [('ps', first)]
+    for k in range(count):
+        i = first + k
+        nxt = k + 1 < count
+        if nxt and streams > 1 and (i + 1) % BATCHES_PER_ITER != 0:
+            order.append(('ps', i + 1))
+            nxt = False
+        order.append(('rest', i))
+        if nxt:
+            order.append(('ps', i + 1))
+    return order
+
+
+def run_path(mf, h, prm, precision, steps, warmup, seed, streams=2):
+    """Time `steps` batches of the full forward path; returns timings and the last batch's ME.
+
+    streams = 2: the phase space of batch i+1 runs on a second HIP stream, into the second
+    of two event buffers, while the matrix element of batch i runs.  Its waves take the
+    compute units that batch i's last matrix-element waves leave idle: 1e6 events are 15.3
+    waves per SIMD.  The matrix elements and the Vegas calls stay on one stream, in batch
+    order, so no two matrix-element launches overlap and each launch's HIP events time that
+    kernel alone.  Events order the two streams:
+      * a buffer is refilled only after the Vegas call that last read it;
+      * a matrix element starts only when its phase space is done;
+      * the first batch of a Vegas iteration waits for the grid refined by the previous one.
+    streams = 1: everything on one stream.
+    """
     pid = mf.PROCESS[PROC]
     d = mf.mf_process_dims(pid)
     dev = torch.device('cuda', 0)
     f64 = dict(dtype=torch.float64, device=dev)
-    p = torch.empty(6, 4, BATCH, **f64)
-    w = torch.empty(BATCH, **f64)
-    jac = torch.empty(BATCH, **f64)
-    pas = torch.empty(BATCH, dtype=torch.uint8, device=dev)
-    bins = torch.empty(d, BATCH, dtype=torch.int16, device=dev)
-    me = torch.empty(BATCH, dtype=torch.float64 if precision == mf.MF_FP64 else torch.float32, device=dev)
     edges = torch.tensor(np.tile(np.linspace(0, 1, NB + 1), (d, 1)), **f64).contiguous()
     acc = torch.zeros(2 + d * NB, **f64)
-    req = [mf.make_request(pid, p, me)]
+    bufs = []
+    for _ in range(streams):
+        b = dict(p=torch.empty(6, 4, BATCH, **f64), w=torch.empty(BATCH, **f64), jac=torch.empty(BATCH, **f64),
+                 pas=torch.empty(BATCH, dtype=torch.uint8, device=dev),
+                 bins=torch.empty(d, BATCH, dtype=torch.int16, device=dev),
+                 me=torch.empty(BATCH, dtype=torch.float64 if precision == mf.MF_FP64 else torch.float32,
+                                device=dev))
+        b['req'] = [mf.make_request(pid, b['p'], b['me'])]
+        b['free'] = torch.cuda.Event()        # recorded after the Vegas call that read the buffer
+        b['ready'] = torch.cuda.Event()       # recorded after the phase space that filled it
+        bufs.append(b)
+    main = torch.cuda.Stream()                # default priority
+    side = torch.cuda.Stream() if streams == 2 else main
+    grid_done = torch.cuda.Event()
     # HIP events around every matrix-element launch of the timed region, recorded on
-    # the stream the library launches on (torch's current stream); read after the end
+    # the stream the library launches it on; read after the end
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
 
-    def step(i, ev=None):
-        mf.mf_phase_space(h, pid, prm, BATCH, seed=seed, offset=i * BATCH, edges=edges, nb=NB, p=p, w=w,
-                          pass_=pas, bin_idx=bins, jac=jac)
-        if ev:
-            ev[0].record()
-        mf.mf_matrix_element(h, req, precision, prm)
-        if ev:
-            ev[1].record()
-        last = (i + 1) % BATCHES_PER_ITER == 0
-        mf.mf_vegas_refine(h, prm, BATCH, d, NB, 1.5, w, jac, me, pas, bins, acc, edges,
-                           update_edges=last, accumulate=(i % BATCHES_PER_ITER) != 0)
+    def phase_space(i):
+        b = bufs[i % streams]
+        with torch.cuda.stream(side):
+            side.wait_event(b['free'])
+            if i % BATCHES_PER_ITER == 0:
+                side.wait_event(grid_done)
+            mf.mf_phase_space(h, pid, prm, BATCH, seed=seed, offset=i * BATCH, edges=edges, nb=NB, p=b['p'],
+                              w=b['w'], pass_=b['pas'], bin_idx=b['bins'], jac=b['jac'])
+            b['ready'].record(side)
 
-    for i in range(warmup):
-        step(i)
+    def rest(i, ev=None):
+        b = bufs[i % streams]
+        with torch.cuda.stream(main):
+            main.wait_event(b['ready'])
+            if ev:
+                ev[0].record(main)
+            mf.mf_matrix_element(h, b['req'], precision, prm)
+            if ev:
+                ev[1].record(main)
+            last = (i + 1) % BATCHES_PER_ITER == 0
+            mf.mf_vegas_refine(h, prm, BATCH, d, NB, 1.5, b['w'], b['jac'], b['me'], b['pas'], b['bins'], acc,
+                               edges, update_edges=last, accumulate=(i % BATCHES_PER_ITER) != 0)
+            b['free'].record(main)
+            if last:
+                grid_done.record(main)
+
+    def run(first, count, timed):
+        for op, i in enqueue_order(first, count, streams):
+            if op == 'ps':
+                phase_space(i)
+            else:
+                rest(i, evs[i - first] if timed else None)
+
+    torch.cuda.synchronize()
+    if warmup:
+        run(0, warmup, False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for i in range(steps):
-        step(warmup + i, evs[i])
+    run(warmup, steps, True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     me_ms = [a.elapsed_time(b) for a, b in evs]
-    return dict(seconds=t1 - t0, me_ms=float(np.mean(me_ms)), me=me, pas=pas, acc=acc)
+    lb = bufs[(warmup + steps - 1) % streams]
+    return dict(seconds=t1 - t0, me_ms=float(np.mean(me_ms)), me=lb['me'], pas=lb['pas'], p=lb['p'], acc=acc,
+                edges=edges)
 
 
 def _best_ms(fn, reps=3):
@@ -219,6 +288,8 @@ def main():
     ap.add_argument('--precision', default='auto')
     ap.add_argument('--no-cpu-baseline', action='store_true')
     ap.add_argument('--no-extras', action='store_true', help='skip the derivative and mixed-batch timings')
+    ap.add_argument('--streams', type=int, default=2, choices=(1, 2),
+                    help='2: the next batch\'s phase space runs on a second stream beside the matrix element')
     ap.add_argument('--seed', type=int, default=4)
     ap.add_argument('--copy-calibration', action='store_true',
                     help=f'also run one {COPY_BYTES >> 20} MiB device-to-device copy (counter calibration)')
@@ -246,8 +317,8 @@ def main():
         prec = mf.MF_FP32_MFMA_BF16
     else:
         prec = mf.PRECISION[args.precision]
-    head = run_path(mf, h, prm, prec, args.steps, args.warmup, args.seed)
-    ref = run_path(mf, h, prm, mf.MF_FP64, args.steps, args.warmup, args.seed)
+    head = run_path(mf, h, prm, prec, args.steps, args.warmup, args.seed, args.streams)
+    ref = run_path(mf, h, prm, mf.MF_FP64, args.steps, args.warmup, args.seed, args.streams)
     # relative difference FP32 vs FP64 on the last batch (same events), events passing cuts
     ok = head['pas'].bool()
     rel = ((head['me'].double() - ref['me']) / ref['me']).abs()[ok]
@@ -276,7 +347,7 @@ def main():
         'data': 'synthetic',
         'config': {'workload': 'gg->ttbar gg at sqrt(s_hat)=1 TeV, m_t=173 GeV, alpha_s=0.118, gluon pT>20 GeV, '
                                '|eta|<2.5, DeltaR>0.4; 1e6-event batches, Vegas refined every 16 batches',
-                   'process': PROC, 'batch': BATCH, 'precision': pname},
+                   'process': PROC, 'batch': BATCH, 'precision': pname, 'streams': args.streams},
         'me_events_per_s': BATCH / (head['me_ms'] * 1e-3),
         'rel_err_fp32_vs_fp64': rel_stats,
         'fp64': {'value': ev_s64, 'ms_per_step': ref['seconds'] / args.steps * 1e3,
