@@ -77,15 +77,16 @@ def measured_traffic(precision_name):
     return float(v) if v else None
 
 
-def flops_per_event(proc, fp64):
-    """Flops per event of the form the FP64 or the FP32 kernels execute (generated-code
+def flops_per_event(proc, precision_name):
+    """Flops per event of the form the kernel of that precision executes (generated-code
     count of the recursion and the colour form, FMA = 2)."""
     import ast
+    key = {'fp64': 'per_event_f64', 'fp32': 'per_event_f32_valu'}.get(precision_name, 'per_event_f32')
     path = os.path.join(ROOT, 'paper_2211_14056_amd', 'csrc', 'generated', 'flops.txt')
     for line in open(path):
         name, rest = line.split(' ', 1)
         if name == proc:
-            return ast.literal_eval(rest)['per_event_f64' if fp64 else 'per_event_f32']
+            return ast.literal_eval(rest)[key]
     raise KeyError(proc)
 
 
@@ -324,14 +325,14 @@ def main():
     rel = ((head['me'].double() - ref['me']) / ref['me']).abs()[ok]
     q = torch.quantile(rel[:100000].float(), torch.tensor([0.5, 0.99], device=rel.device)).tolist()
     rel_stats = dict(median=q[0], p99=q[1], max=float(rel.max()), events=int(ok.sum()))
-    fl = flops_per_event(PROC, prec == mf.MF_FP64)
-    fl64 = flops_per_event(PROC, True)
+    pname = [k for k, v in mf.PRECISION.items() if v == prec][0]
+    fl = flops_per_event(PROC, pname)
+    fl64 = flops_per_event(PROC, 'fp64')
     ev_s = args.steps * BATCH / head['seconds']
     ev_s64 = args.steps * BATCH / ref['seconds']
     me_ach = fl * BATCH / (head['me_ms'] * 1e-3)
     me_ach64 = fl64 * BATCH / (ref['me_ms'] * 1e-3)
     dt = 'f32'
-    pname = [k for k, v in mf.PRECISION.items() if v == prec][0]
     out = {
         'metric': METRIC,
         'value': ev_s,

@@ -119,8 +119,9 @@ int mf_process_dims(int proc);
  *     persistent launch (0, the default: as many as the process's kernel fits);
  *     < 0 leaves it unchanged.
  *   batch_persistent: 1 = the requests of a call are served by persistent
- *     launches, one per gg process class, each pulling 64-event tiles from a
- *     queue (default); 0 = one launch per request; < 0 = unchanged.
+ *     launches, one per gg process class, each pulling tiles of one or more
+ *     64-event waves from a queue (default); 0 = one launch per request;
+ *     < 0 = unchanged.
  * Errors: MF_ERR_INVALID_ARG for out-of-range values. */
 mf_status mf_set_launch(mf_handle h, int proc, int precision, int block, int batch_waves_per_cu,
                         int batch_persistent);
@@ -130,8 +131,9 @@ mf_status mf_set_launch(mf_handle h, int proc, int precision, int block, int bat
 mf_status mf_failures(mf_handle h, uint64_t* count);
 
 /*
- * mf_phase_space -- rows a1..a4 of the hot path: uniforms, Vegas map,
- * RAMBO-on-diet phase space with massive rescaling, generation cuts.
+ * mf_phase_space -- the sampling steps of the path (sect. 1; sect. 3 for the
+ * cuts): uniforms, Vegas map, RAMBO-on-diet phase space with massive
+ * rescaling, generation cuts.
  *   x          [d][n] uniforms, or NULL to draw them from Philox4x32-10 with
  *              key = seed and counter = (offset + *offset_dev + event, dim/2);
  *   offset_dev optional device pointer added to offset (lets a captured graph
@@ -153,8 +155,11 @@ mf_status mf_phase_space(mf_handle h, int proc, const mf_params* prm, int64_t n,
                          double* x_out, void* stream);
 
 /*
- * mf_matrix_element -- row a5 (+ a6 colour contraction): |M|^2 for each event
- * of each request.  With n_reqs > 1 all requests are served by one launch.
+ * mf_matrix_element -- the helicity-summed, colour-contracted tree-level |M|^2
+ * of each event of each request (sect. 2: the matrix element the paper's
+ * generated code evaluates per event).  With n_reqs > 1 and batch_persistent
+ * set, the gg requests are served by one persistent launch per process class
+ * (mf_set_launch); otherwise one launch per request.
  * Errors: MF_ERR_INVALID_ARG for n_reqs < 1, NULL reqs/prm, a bad process or
  * precision, n < 0, or NULL p / me_out with n > 0.
  */
@@ -162,12 +167,13 @@ mf_status mf_matrix_element(mf_handle h, const mf_request* reqs, int n_reqs, int
                             const mf_params* prm, void* stream);
 
 /*
- * mf_matrix_element_vjp -- row a9: vector-Jacobian product of |M|^2 with
+ * mf_matrix_element_vjp -- vector-Jacobian product of |M|^2 with
  * respect to the uniforms x (through the Vegas map `edges`, which may be NULL
  * for the identity, and the phase space) and to (m_t, alpha_s).  The forward
- * value is written to me_out when it is not NULL.  Per helicity the forward
- * recursion is recomputed in registers and swept in reverse; no
- * intermediate current is stored in memory.
+ * value is written to me_out when it is not NULL.  The derivative is taken
+ * in forward (tangent) mode, one pass per input direction: per helicity the
+ * recursion is re-run in registers with dual numbers, and no intermediate
+ * current is stored in memory.
  * Errors: as mf_matrix_element, plus NULL x / grad_me / grad_x / grad_theta,
  * MF_ERR_UNSUPPORTED for MF_EE_MUMU.
  */
@@ -175,7 +181,7 @@ mf_status mf_matrix_element_vjp(mf_handle h, const mf_request* reqs, int n_reqs,
                                 const mf_params* prm, const double* edges, int nb, void* stream);
 
 /*
- * mf_vegas_refine -- rows a7 and a8: forms F = flux * w * jac * me * pass with
+ * mf_vegas_refine -- the Vegas step (sect. 1): forms F = flux * w * jac * me * pass with
  * flux = (hbar c)^2 / (2 s) in pb GeV^2 / GeV^2 (so F is in pb), reduces
  * acc[0] = sum F, acc[1] = sum F^2, acc[2 + k*nb + i] = sum of F^2 over events
  * in bin i of dimension k (deterministic order).  flags:

@@ -162,7 +162,8 @@ class Handle:
 
 def mf_phase_space(h, proc, prm, n, x=None, seed=0, offset=0, offset_dev=None, edges=None, nb=50,
                    p=None, w=None, pass_=None, bin_idx=None, jac=None, x_out=None, stream=None):
-    """Rows a1-a4; returns dict of output tensors (allocated here when not given)."""
+    """Uniforms, Vegas map, phase space and cuts; returns a dict of output tensors
+    (allocated here when not given)."""
     dev = torch.device('cuda', h.device)
     n_ext = mf_process_legs(proc)
     d = mf_process_dims(proc)

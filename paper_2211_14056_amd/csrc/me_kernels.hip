@@ -1,5 +1,7 @@
-// Matrix-element kernels: one lane per event, the whole helicity sum, the
-// colour-ordered recursion and the colour contraction fused in registers.
+// Matrix-element kernels: one lane per event, the helicity sum (half of the
+// gluon-helicity configurations evaluated, their reverses supplied by the
+// reversal symmetry), the colour-ordered recursion and the colour contraction
+// fused in registers.
 //
 // The paper's custom operator launches one GPU kernel per spinor, vertex and
 // propagator, passing every intermediate through device memory (sect. 2),

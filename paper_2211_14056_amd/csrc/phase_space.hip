@@ -27,7 +27,7 @@ __global__ __launch_bounds__(256) void k_phase_space(PsArgs a)
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= a.n) return;
     const int64_t n = a.n;
-    // ---- a1: uniforms
+    // ---- uniforms
     double x[D];
     if (a.x) {
 #pragma unroll
@@ -40,7 +40,7 @@ __global__ __launch_bounds__(256) void k_phase_space(PsArgs a)
 #pragma unroll
         for (int k = 0; k < D; ++k) a.x_out[k * n + e] = x[k];
     }
-    // ---- a2: Vegas map
+    // ---- Vegas map
     double y[D];
     double jac = 1.0;
     if (a.edges) {
@@ -66,13 +66,13 @@ __global__ __launch_bounds__(256) void k_phase_space(PsArgs a)
             }
         }
     }
-    // ---- a3: RAMBO on diet + massive rescaling
+    // ---- RAMBO on diet + massive rescaling
     const double rs = a.sqrt_s;
     double P[NOUT][4];
     double wgt = 0.0;
     const bool ok = rambo_event<NOUT, double>(y, rs, a.m_out, P, &wgt);
     if (!ok && a.fail_count) atomicAdd(a.fail_count, 1ull);
-    // ---- a4: cuts on the final gluons (outgoing index >= 2 for the gg processes)
+    // ---- cuts on the final gluons (outgoing index >= 2 for the gg processes)
     bool pass = true;
     if (a.pass) {
         double eta_[2] = {0.0, 0.0}, phi_[2] = {0.0, 0.0};

@@ -25,6 +25,11 @@ lanes k+1 and k+2 of its quad by DPP and sums three pieces:
 * the block with k+2, once (lane k+2 computes the transposed block).
 
 The four lanes together give exactly the full quadratic form.
+
+Helicities.  As in the one-lane body, only the configurations in which gluon
+k-1 (an actual gluon, not a slot) has helicity +1 are evaluated; their reverses
+give the same colour-summed |M|^2 and are accounted for by a factor 2 in the
+normalisation.
 """
 import itertools
 import math
@@ -199,7 +204,7 @@ def emit_split(proc, lds_budget, opaque_inputs=True, group_barriers=True, stream
     if opaque_inputs:
         opq = [f'opaque(K{j}[{c}]);' for j in range(k) for c in range(4)] + [f'opaque(PT[{c}]);' for c in range(4)]
     body.append('#pragma unroll 1')
-    body.append(f'for (int gconf = 0; gconf < {2 ** k}; ++gconf) {{')
+    body.append(f'for (int gconf = {2 ** (k - 1)}; gconf < {2 ** k}; ++gconf) {{   // gluon {k - 1}: helicity +1')
     body += ['    ' + l for l in opq]
     for j in range(k):
         body.append(f'    const R lam{j} = (gconf >> hb[{j}]) & 1 ? R(1) : R(-1);')
@@ -218,7 +223,7 @@ def emit_split(proc, lds_budget, opaque_inputs=True, group_barriers=True, stream
     body.append('}')
     out += ['    ' + l for l in body]
     out.append('}')
-    per_lane = (2 ** k) * (gluon_flops + 2 * (quark_flops + colour_flops))
+    per_lane = (2 ** (k - 1)) * (gluon_flops + 2 * (quark_flops + colour_flops))
     info = dict(lds_slots=8 * len(lds_slot), currents=len(need), gluon_per_gconf=gluon_flops,
                 quark_per_top_hel=quark_flops, colour_per_top_hel=colour_flops,
                 executed_per_event=4 * per_lane)

@@ -429,12 +429,19 @@ def emit_qcd(proc, with_colour=True, opaque_inputs=True, group_barriers=True, ld
       as its coefficients are formed (fewer values live at once; same arithmetic).
     share_products: form a quark-line product Q(prefix) Jslash(block) used by several
       orderings once (see Recursion.start_quark_line).
+
+    Helicity sum.  For real momenta, reversing every helicity turns each partial
+    amplitude into its complex conjugate times one phase common to all orderings,
+    so a configuration and its reverse have the same colour-summed |M|^2.  The body
+    therefore runs only the gluon-helicity configurations in which the last gluon
+    has helicity +1 (2^(k-1) of them; both top and antitop helicities each), and the
+    normalisation constant carries the factor 2 for the reversed half.
     """
     k = proc.k
     out = []
     fn = f'me_{proc.name}'
     out.append(f'// ---- {proc.name}: {k} gluons, {math.factorial(k)} colour orderings, '
-               f'{2 ** (k + 2)} helicities')
+               f'{2 ** (k + 2)} helicities, {2 ** (k + 1)} evaluated (the rest by helicity reversal)')
     out.append(f'template <typename R, typename KT, typename Sink>')
     lds_arg = ', R* __restrict__ lds' if lds_budget else ''
     out.append(f'__device__ __forceinline__ void {fn}_body(const KT (&p)[{proc.n_ext}][4], '
@@ -576,7 +583,7 @@ def emit_qcd(proc, with_colour=True, opaque_inputs=True, group_barriers=True, ld
             opq += [f'opaque(K{gi}[{c}]);' for c in comps]
         opq += [f'opaque(PT[{c}]);' for c in range(4)]
     body.append('#pragma unroll 1')
-    body.append(f'for (int gconf = 0; gconf < {2 ** k}; ++gconf) {{')
+    body.append(f'for (int gconf = {2 ** (k - 1)}; gconf < {2 ** k}; ++gconf) {{   // last gluon: helicity +1')
     body += ['    ' + l for l in opq]
     for gi in range(k):
         body.append(f'    const R lam{gi} = (gconf >> {gi}) & 1 ? R(1) : R(-1);')
@@ -607,16 +614,16 @@ def emit_qcd(proc, with_colour=True, opaque_inputs=True, group_barriers=True, ld
     if not with_colour or not constants:
         return '\n'.join(out), dict(lds_slots=nslots)
     out.append('')
-    out.append(f'// normalisation: g^(2k) / (avg * sym * colour denominator)')
+    out.append(f'// normalisation: 2 (reversed helicities) / (avg * sym * colour denominator); times g^(2k)')
     out.append(f'__host__ __device__ constexpr double {fn}_norm_noalpha() '
-               f'{{ return 1.0 / ({proc.avg!r} * {float(proc.sym)!r} * {float(proc.cden)!r}); }}')
+               f'{{ return 2.0 / ({proc.avg!r} * {float(proc.sym)!r} * {float(proc.cden)!r}); }}')
     out.append(f'constexpr int {fn}_k = {k};')
     out.append(f'constexpr int {fn}_ncolour = {n_or};')
     helis = 2 ** (k + 2)
     flops = dict(gluon_per_gconf=gluon_flops, quark_per_top_hel=quark_flops,
                  colour_per_hel=colour_flops // 2,
-                 per_event=(2 ** k) * (gluon_flops + 2 * (quark_flops + colour_flops)),
-                 helicities=helis, lds_slots=nslots)
+                 per_event=(2 ** (k - 1)) * (gluon_flops + 2 * (quark_flops + colour_flops)),
+                 helicities=helis, evaluated_helicities=helis // 2, lds_slots=nslots)
     out.append(f'// flops per event (generated count): {flops}')
     return '\n'.join(out), flops
 
@@ -639,6 +646,11 @@ LDS_QUAD_F64 = 152
 # keeps the plain form.
 SHARE_F32 = True
 SHARE_F64 = False
+# The FP32 body with the colour form on the VALU does not share products: its
+# build with them (half helicity loop) returned wrong, run-to-run varying values
+# on the GPU, while the same source is exact on the CPU.  Without them it has
+# no spill and is deterministic; it costs 6%.
+SHARE_F32_VALU = False
 
 
 def _variant(proc, name, suffix, **kw):
@@ -659,7 +671,7 @@ def emit_all(outdir, **opts):
         extra = []
         if lds:
             s32, i32 = _variant(proc, name, 'body_lds32', with_colour=True, lds_budget=LDS_F32, constants=False,
-                                share_products=SHARE_F32, **opts)
+                                share_products=SHARE_F32_VALU, **opts)
             s64, i64 = _variant(proc, name, 'body_lds64', with_colour=True, lds_budget=LDS_F64, constants=False,
                                 share_products=SHARE_F64, **opts)
             extra = [s32, s64,
@@ -671,6 +683,7 @@ def emit_all(outdir, **opts):
         # flops per event of the forms the kernels execute (colour form counted in both)
         flops['per_event_f64'] = emit_qcd(proc, share_products=SHARE_F64 and lds)[1]['per_event']
         flops['per_event_f32'] = emit_qcd(proc, share_products=SHARE_F32)[1]['per_event']
+        flops['per_event_f32_valu'] = emit_qcd(proc, share_products=SHARE_F32_VALU and lds)[1]['per_event']
         cnum, cden = proc.cnum, proc.cden
         ctab = [f'// colour matrix numerators for {name} (denominator {cden})',
                 f'static __constant__ const short me_{name}_cnum[{len(cnum)}][{len(cnum)}] = {{']
@@ -689,7 +702,7 @@ def emit_all(outdir, **opts):
                 f.write('// Generated by paper_2211_14056_amd.gen.lane_split -- do not edit.\n')
                 f.write(src_q + '\n\n' + f'constexpr int me_{name}_quad_slots = {info_q["lds_slots"]};\n')
                 f.write(f'__host__ __device__ constexpr double me_{name}_quad_norm_noalpha() '
-                        f'{{ return 1.0 / ({proc.avg!r} * {float(proc.sym)!r} * {float(proc.cden)!r}); }}\n')
+                        f'{{ return 2.0 / ({proc.avg!r} * {float(proc.sym)!r} * {float(proc.cden)!r}); }}\n')
             flops['quad_executed_per_event'] = info_q['executed_per_event']
         summary[name] = flops
     with open(os.path.join(outdir, 'flops.txt'), 'w') as f:

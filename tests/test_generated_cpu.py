@@ -87,6 +87,7 @@ CASES = [
     ('gg_ttgg', 6, dict(), 4),
     ('gg_ttgg', 6, dict(share_products=True), 4),
     ('gg_ttgg', 6, dict(share_products=True, lds_budget=152), 4),
+    ('gg_ttgg', 6, dict(lds_budget=152), 4),
 ]
 
 

@@ -79,7 +79,7 @@ def oracle_me(proc, p_gpu_layout):
     return integrand.me(proc, p, par_of(proc)).numpy()
 
 
-# ------------------------------------------------------------------ a1: RNG
+# ------------------------------------------------------------------ RNG
 @pytest.mark.parametrize('proc', PROCS)
 def test_uniforms_bitwise(h, proc):
     n = 5000 + 37
@@ -89,7 +89,7 @@ def test_uniforms_bitwise(h, proc):
     assert np.array_equal(ev['x'].cpu().numpy(), x_ref)
 
 
-# ------------------------------------------------------------------ a2-a4: phase space
+# ------------------------------------------------------------------ phase space
 @pytest.mark.parametrize('proc', PROCS)
 def test_phase_space_vs_oracle(h, proc):
     n = 4096 + 17
@@ -135,7 +135,7 @@ def test_phase_space_conservation_full_size(h):
     assert h.failures() == 0
 
 
-# ------------------------------------------------------------------ a5: matrix element
+# ------------------------------------------------------------------ matrix element
 ME_N = {'ee_mumu': 2000, 'gg_tt': 2000, 'gg_ttg': 300, 'gg_ttgg': 40}
 
 
@@ -267,6 +267,25 @@ def test_me_fp32_forms_vs_fp64_every_event_full_size(h):
         assert float(rel.median()) < 1e-5 and float(rel.max()) < 1e-3
 
 
+def test_me_forms_bitwise_repeatable_full_size(h):
+    """Each matrix-element form, launched three times on the same 10^6 gg -> ttbar gg events,
+    returns bit-identical values.  Every event is computed by one lane (or one quad) alone, in
+    a fixed order, so a difference between launches can only come from a build whose results
+    depend on timing; such a build is also wrong on some events.  After a small launch first,
+    so that the kernels do not start from their own previous state."""
+    small = gpu_events(h, 'gg_ttgg', 43, seed=22)
+    n = 1_000_000
+    ev = gpu_events(h, 'gg_ttgg', n, seed=4)
+    for prec in (mf.MF_FP32, mf.MF_FP32_MFMA_F32, mf.MF_FP32_MFMA_BF16, mf.MF_FP64):
+        say('  repeatability, precision', prec)
+        mf.matrix_element(h, mf.MF_GG_TTGG, small['p'], prec)
+        outs = [mf.matrix_element(h, mf.MF_GG_TTGG, ev['p'], prec) for _ in range(3)]
+        torch.cuda.synchronize()
+        assert bool(torch.isfinite(outs[0]).all())
+        for o in outs[1:]:
+            assert torch.equal(o, outs[0]), int((o != outs[0]).sum())
+
+
 def test_me_lorentz_invariance_fp64(h):
     n = 512
     say('lorentz gg_ttgg', n)
@@ -344,7 +363,7 @@ def test_me_ttgg_quad_layout_full_size(h):
     assert e.shape == (0,)
 
 
-# ------------------------------------------------------------------ a7-a8: Vegas
+# ------------------------------------------------------------------ Vegas
 def test_vegas_refine_vs_oracle(h):
     proc = 'gg_ttg'
     n = 20000 + 11
@@ -449,7 +468,7 @@ def test_vegas_pull_distribution(h):
         assert 0.5 < pulls.std(ddof=1) < 1.5
 
 
-# ------------------------------------------------------------------ a9: derivative
+# ------------------------------------------------------------------ derivative
 def _vjp_gpu(h, proc, x, gbar, precision, edges=None):
     pid = mf.PROCESS[proc]
     d, n = x.shape
@@ -599,7 +618,7 @@ def test_oversized_request_rejected_before_launch(h):
     assert st == -1 and b'2^36' in mf.lib().mf_last_error()
 
 
-# ------------------------------------------------------------------ a10: persistent batch, graphs, tuning
+# ------------------------------------------------------------------ persistent batch, graphs, tuning
 def _mixed_requests(h, spec, precision, seed0=200):
     reqs, outs, evs = [], [], []
     for i, (proc, n) in enumerate(spec):

@@ -5,6 +5,8 @@
 * explicit colour (all Feynman diagrams, explicit SU(3) indices) == colour-ordered form.
 * gluon Ward identity (eps -> k) for every partial amplitude and the full amplitude.
 * Lorentz invariance under boosts and rotations; Bose symmetry; alpha_s scaling.
+* helicity reversal: A_sigma(-h) = eta conj(A_sigma(h)), one unimodular eta for all
+  orderings, so |M_h|^2 = |M_-h|^2 with massive tops (the kernels sum half and double).
 * cross sections vs closed forms within the Monte Carlo error.
 * reverse-mode gradient vs central finite differences.
 * planted mistakes (a flipped vertex sign, a dropped mass term, a wrong colour
@@ -211,6 +213,37 @@ def test_bose_symmetry(proc, N):
         r = p.clone()
         r[:, [4, 5]] = p[:, [5, 4]]
         assert ((me_ordered.matrix_element(proc, r, P) / a - 1).abs()).max() < 1e-12
+
+
+@pytest.mark.parametrize('proc,N', [('gg_tt', 20), ('gg_ttg', 6), ('gg_ttgg', 3)])
+def test_helicity_reversal_conjugates_partial_amplitudes(proc, N):
+    """Reversing every helicity (gluons, top and antitop) maps each partial amplitude to
+    its complex conjugate times one unimodular factor shared by all colour orderings, so
+    the colour-summed |M_h|^2 of a configuration equals that of its reverse.  With the
+    tops massive this is not a spinor-product identity but follows from the real
+    momenta and the helicity basis; a polarisation vector or spinor with a wrong sign
+    or phase breaks it.  The kernels evaluate half of the configurations and double."""
+    p = events(proc, N, 21)
+    hels = me_ordered.helicities(proc)
+    assert P['m_t'] > 100                                # massive tops, not the massless limit
+    _, per = me_ordered.matrix_element(proc, p, P, return_per_helicity=True)
+    index = {tuple(h): i for i, h in enumerate(hels)}
+    scale = per.abs().amax(-1, keepdim=True)
+    for h, i in index.items():
+        rev = tuple(-v for v in h)
+        assert ((per[:, i] - per[:, index[rev]]).abs() / scale[:, 0]).max() < 1e-12
+        if h[-1] != 1:                                   # each pair once
+            continue
+        A = me_ordered.partial_amplitudes(p, h, P)
+        B = me_ordered.partial_amplitudes(p, rev, P)
+        big = A.abs() > 1e-6 * A.abs().amax(-1, keepdim=True)
+        eta = torch.where(big, B / A.conj(), torch.zeros_like(B))
+        ref = eta.gather(1, big.to(torch.int64).argmax(1, keepdim=True))
+        assert ((eta.abs() - 1).abs()[big]).max() < 1e-10
+        assert ((eta - ref).abs()[big]).max() < 1e-10
+    # half the configurations, doubled, give the full sum
+    last = torch.tensor([h[-1] == 1 for h in hels])
+    assert ((2 * per[:, last].sum(-1) / per.sum(-1) - 1).abs()).max() < 1e-12
 
 
 @pytest.mark.parametrize('proc,k', [('gg_tt', 2), ('gg_ttg', 3), ('gg_ttgg', 4)])
