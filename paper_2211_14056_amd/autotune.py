@@ -13,6 +13,9 @@ keyed by (GPU architecture, process, precision, batch-size bucket).
 Environment: MF_TUNE = off | use | search (default use: apply cached entries,
 tune nothing); MF_TUNE_CACHE = path of the cache (default
 ~/.cache/mfhip/tuning.json).
+
+`python -m paper_2211_14056_amd.autotune --report` prints the measured curves
+(events/s against block size, event layout and persistent grid) as markdown.
 """
 import json
 import math
@@ -20,7 +23,8 @@ import os
 
 import torch
 
-from . import (MF_FP64, PROCESS, make_request, mf_matrix_element, mf_phase_space, mf_process_legs, params)
+from . import (MF_FP64, PRECISION, PROCESS, make_request, mf_matrix_element, mf_phase_space, mf_process_legs,
+               params)
 
 BLOCKS = (64, 128, 192, 256)
 WAVES_PER_CU = (0, 1, 2, 4)     # 0 = as many as fit
@@ -137,3 +141,48 @@ def tune(h, procs=('gg_tt', 'gg_ttg'), precisions=(MF_FP64,), n=1 << 18, batch=N
     if mode == 'search':
         _save(cache)
     return used
+
+
+def report(h, sizes=(1 << 16, 1 << 20), precisions=('fp64', 'fp32', 'fp32_mfma_bf16')):
+    """Markdown tables of the sweeps on this device; resets the handle to its defaults afterwards."""
+    lines = [f'Device: {torch.cuda.get_device_name(0)} ({arch()}); best of 3 launches after one warm-up.', '',
+             '## Block size (single-request launch, events/s in millions)', '',
+             '| process | precision | events | ' + ' | '.join(f'block {b}' for b in BLOCKS) + ' | best |',
+             '|---|---|---|' + '---|' * len(BLOCKS) + '---|']
+    for proc in ('gg_tt', 'gg_ttg'):
+        for pname in precisions:
+            for n in sizes:
+                t = sweep_block(h, proc, PRECISION[pname], n)
+                best = min(t, key=t.get)
+                lines.append(f'| {proc} | {pname} | {n} | ' + ' | '.join(f'{n / t[b] / 1e3:.1f}' for b in BLOCKS)
+                             + f' | {best} |')
+                h.set_launch(PROCESS[proc], PRECISION[pname], 0)
+    n = 1 << 20
+    t = sweep_block(h, 'gg_ttgg', MF_FP64, n, blocks=(64, 256))
+    h.set_launch(PROCESS['gg_ttgg'], MF_FP64, 0)
+    lines += ['', '## Event layout, gg -> ttbar gg in FP64 (events/s in millions)', '',
+              '| events | one lane per event | four lanes per event |', '|---|---|---|',
+              f'| {n} | {n / t[64] / 1e3:.1f} | {n / t[256] / 1e3:.1f} |']
+    from .workloads import mixed_batch
+    spec = mixed_batch(64, seed=5)
+    total = sum(k for _, k in spec)
+    lines += ['', f'## Persistent mixed batch: 64 requests, {total} events, fp32_mfma_bf16 (ms per call)', '',
+              '| grid | ms | events/s (millions) |', '|---|---|---|']
+    t = sweep_batch(h, spec, PRECISION['fp32_mfma_bf16'])
+    for k, v in t.items():
+        label = 'one launch per request' if k == 'per_request' else \
+            f"persistent, {k.split('_')[1]} one-wave blocks per CU" + (' (as many as fit)' if k.endswith('_0') else '')
+        lines.append(f'| {label} | {v:.2f} | {total / v / 1e3:.0f} |')
+    h.set_launch(batch_waves_per_cu=0, batch_persistent=1)
+    return '\n'.join(lines)
+
+
+if __name__ == '__main__':
+    import argparse
+    ap = argparse.ArgumentParser(description=__doc__.split('\n')[0])
+    ap.add_argument('--report', action='store_true', help='print the measured sweep curves as markdown')
+    args = ap.parse_args()
+    if args.report:
+        from . import Handle
+        torch.cuda.init()
+        print(report(Handle(0)), flush=True)
