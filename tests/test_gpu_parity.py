@@ -248,18 +248,19 @@ def test_me_full_size_sampled(h, proc, n):
             assert rel[ok].max() < 1e-3
 
 
-def test_me_fp32_forms_vs_fp64_every_event_full_size(h):
-    """Every event of a 10^6-event gg -> ttbar gg batch (the benchmark launch): each FP32 form
-    (VALU colour, FP32-MFMA colour, BF16x3-MFMA colour) against the FP64 kernel, which the
-    tests above pin to the oracle.  Bars on the events passing the cuts: median 1e-5, max 1e-3.
+@pytest.mark.parametrize('proc,n', [('gg_ttgg', 1_000_000), ('gg_ttg', 4_000_000), ('gg_tt', 4_000_000)])
+def test_me_fp32_forms_vs_fp64_every_event_full_size(h, proc, n):
+    """Every event of a full-size batch (10^6 gg -> ttbar gg events: the benchmark launch): each
+    FP32 form (VALU colour, FP32-MFMA colour, BF16x3-MFMA colour) against the FP64 kernel, which
+    the tests above pin to the oracle.  Bars on the events passing the cuts: median 1e-5, max 1e-3.
     Checking all events, not a sample, would expose a kernel build that is wrong on a subset."""
-    n = 1_000_000
-    say('me fp32 forms vs fp64, every event', n)
-    ev = gpu_events(h, 'gg_ttgg', n, seed=4)
-    ref = mf.matrix_element(h, mf.MF_GG_TTGG, ev['p'], mf.MF_FP64)
+    pid = mf.PROCESS[proc]
+    say('me fp32 forms vs fp64, every event', proc, n)
+    ev = gpu_events(h, proc, n, seed=4)
+    ref = mf.matrix_element(h, pid, ev['p'], mf.MF_FP64, prm_of(proc))
     ok = ev['pass_'].bool()
     for prec in (mf.MF_FP32, mf.MF_FP32_MFMA_F32, mf.MF_FP32_MFMA_BF16):
-        me = mf.matrix_element(h, mf.MF_GG_TTGG, ev['p'], prec)
+        me = mf.matrix_element(h, pid, ev['p'], prec, prm_of(proc))
         torch.cuda.synchronize()
         assert bool(torch.isfinite(me).all())
         rel = ((me.double() - ref) / ref).abs()[ok]
@@ -267,19 +268,20 @@ def test_me_fp32_forms_vs_fp64_every_event_full_size(h):
         assert float(rel.median()) < 1e-5 and float(rel.max()) < 1e-3
 
 
-def test_me_forms_bitwise_repeatable_full_size(h):
-    """Each matrix-element form, launched three times on the same 10^6 gg -> ttbar gg events,
-    returns bit-identical values.  Every event is computed by one lane (or one quad) alone, in
-    a fixed order, so a difference between launches can only come from a build whose results
-    depend on timing; such a build is also wrong on some events.  After a small launch first,
-    so that the kernels do not start from their own previous state."""
-    small = gpu_events(h, 'gg_ttgg', 43, seed=22)
-    n = 1_000_000
-    ev = gpu_events(h, 'gg_ttgg', n, seed=4)
+@pytest.mark.parametrize('proc,n', [('gg_ttgg', 1_000_000), ('gg_ttg', 4_000_000), ('gg_tt', 4_000_000)])
+def test_me_forms_bitwise_repeatable_full_size(h, proc, n):
+    """Each matrix-element form, launched three times on the same full-size batch, returns
+    bit-identical values.  Every event is computed by one lane (or one quad) alone, in a fixed
+    order, so a difference between launches can only come from a build whose results depend on
+    timing; such a build is also wrong on some events.  After a small launch first, so that the
+    kernels do not start from their own previous state."""
+    small = gpu_events(h, proc, 43, seed=22)
+    ev = gpu_events(h, proc, n, seed=4)
     for prec in (mf.MF_FP32, mf.MF_FP32_MFMA_F32, mf.MF_FP32_MFMA_BF16, mf.MF_FP64):
-        say('  repeatability, precision', prec)
-        mf.matrix_element(h, mf.MF_GG_TTGG, small['p'], prec)
-        outs = [mf.matrix_element(h, mf.MF_GG_TTGG, ev['p'], prec) for _ in range(3)]
+        say('  repeatability', proc, n, 'precision', prec)
+        pid = mf.PROCESS[proc]
+        mf.matrix_element(h, pid, small['p'], prec, prm_of(proc))
+        outs = [mf.matrix_element(h, pid, ev['p'], prec, prm_of(proc)) for _ in range(3)]
         torch.cuda.synchronize()
         assert bool(torch.isfinite(outs[0]).all())
         for o in outs[1:]:
