@@ -44,9 +44,10 @@ COPY_BYTES = 512 << 20
 
 
 # sources of the two timed matrix-element kernels (the matrix-core-colour kernel
-# and the FP64 kernel), generated process code included
+# and the FP64 kernel, two lanes per event), generated process code included
 ME_SOURCES = ('me_kernels.hip', 'me_mfma.hip', 'me_mfma_colour.h', 'me_common.h', 'dual.h', 'internal.h',
-              'generated/me_gg_tt.inc', 'generated/me_gg_ttg.inc', 'generated/me_gg_ttgg.inc')
+              'me_ttgg_pair.hip', 'generated/me_gg_tt.inc', 'generated/me_gg_ttg.inc',
+              'generated/me_gg_ttgg.inc', 'generated/me_gg_ttgg_pair.inc')
 
 
 def source_hash():

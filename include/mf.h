@@ -111,9 +111,12 @@ int mf_process_dims(int proc);
  *   proc >= 0: threads per block for single-request launches of (proc,
  *     precision), 64..256 in steps of 64, 0 = library default.  The
  *     gg -> ttbar gg kernels always run one-wave blocks (their LDS is per wave);
- *     for them the value selects the event layout instead: in FP64, 256 = four
- *     lanes per event (colour orderings split by first gluon, gluon currents
- *     shared within the quad), any other value = one lane per event (default).
+ *     for them the value selects the event layout instead: in FP64, 128 (and 0,
+ *     the default) = two lanes per event (colour orderings split in pairs
+ *     related by swapping both the beams and the final gluons, currents and
+ *     amplitudes exchanged within the pair), 256 = four lanes per event
+ *     (orderings split by first gluon, currents shared within the quad),
+ *     64 or 192 = one lane per event.
  *     proc < 0 leaves the per-process settings unchanged.
  *   batch_waves_per_cu >= 0: one-wave blocks per compute unit in each
  *     persistent launch (0, the default: as many as the process's kernel fits);

@@ -51,8 +51,12 @@ hipError_t launch_matrix_element_mfma(const MeJob& j, int precision, double mt, 
                                       hipStream_t s);
 // g g -> t tbar g g in FP64 with four lanes per event; `coupling` = (4 pi alpha_s)^4
 hipError_t launch_ttgg_quad(const MeJob& j, double mt, double coupling, hipStream_t s);
-// launch-configuration value of mf_set_launch that selects the four-lanes-per-event
-// layout for g g -> t tbar g g in FP64
+// g g -> t tbar g g in FP64 with two lanes per event (the default layout)
+hipError_t launch_ttgg_pair(const MeJob& j, double mt, double coupling, hipStream_t s);
+// launch-configuration values of mf_set_launch that select the layout of g g -> t tbar g g
+// in FP64: two lanes per event (also 0, the default), four lanes per event; other values
+// select one lane per event
+constexpr int TTGG_PAIR_LAYOUT = 128;
 constexpr int TTGG_QUAD_LAYOUT = 256;
 
 constexpr int MAX_BATCH = 64;

@@ -167,6 +167,21 @@ __device__ __forceinline__ double quad_rot(double x)
     return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
 }
 
+// Value held by the other lane of this lane's pair (lanes 2j, 2j+1), by a DPP
+// quad permutation [1, 0, 3, 2].  Both lanes of the pair must be active.
+__device__ __forceinline__ int pair_swap_bits(int x) { return __builtin_amdgcn_update_dpp(0, x, 0xB1, 0xF, 0xF, false); }
+__device__ __forceinline__ float pair_swap(float x)
+{
+    return __builtin_bit_cast(float, pair_swap_bits(__builtin_bit_cast(int, x)));
+}
+__device__ __forceinline__ double pair_swap(double x)
+{
+    const unsigned long long v = __builtin_bit_cast(unsigned long long, x);
+    const unsigned lo = (unsigned)pair_swap_bits((int)(unsigned)v);
+    const unsigned hi = (unsigned)pair_swap_bits((int)(unsigned)(v >> 32));
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
 // Helicity-sum accumulator used by the VALU colour path.
 template <typename R>
 struct HelicitySum {

@@ -171,6 +171,8 @@ hipError_t launch_matrix_element(const MeJob& j, int precision, double mt, doubl
     }
     if (j.proc == GG_TTGG && precision == 0 && block == TTGG_QUAD_LAYOUT)
         return launch_ttgg_quad(j, mt, coupling, s);
+    if (j.proc == GG_TTGG && precision == 0 && (block <= 0 || block == TTGG_PAIR_LAYOUT))
+        return launch_ttgg_pair(j, mt, coupling, s);
     if (block <= 0) block = 256;
     switch (precision) {
     case 0: return launch_valu<double>(j, mt, coupling, block, s);

@@ -113,13 +113,16 @@ class Recursion:
     currents parked in LDS to their slots.
     """
 
-    def __init__(self, b, moms, eps, lds_slot, stream=False, local_memo=False, remote=None):
+    def __init__(self, b, moms, eps, lds_slot, stream=False, local_memo=False, remote=None,
+                 exchange='quad_rot<{m}>'):
         self.b, self.moms, self.eps, self.lds_slot = b, moms, eps, lds_slot
         self.stream = stream
         self.local_memo = local_memo
         # remote(rho) -> None, or (t, M, sign): J(rho) = sign * [J(t) of the lane M places
-        # further in the quad] (lanes that share an event, see lane_split)
+        # further in the group of lanes that share an event (see lane_split); `exchange`
+        # is the device function that reads a value from that lane
         self.remote = remote
+        self.exchange = exchange
         self.msum_memo, self.dot_memo, self.jmemo = {}, {}, {}
 
     @staticmethod
@@ -174,14 +177,15 @@ class Recursion:
         return vec
 
     def _received(self, t, m, sign):
-        """Current read from another lane of the quad (DPP), with a reflection sign."""
+        """Current read from another lane sharing the event (DPP), with a reflection sign."""
         b = self.b
         own = self.J(t)
+        fn = self.exchange.format(m=m)
 
         def rot(x):
             if x.is_const:
                 return x
-            v = b.new(f'quad_rot<{m}>({b.ref(x)})', 0)
+            v = b.new(f'{fn}({b.ref(x)})', 0)
             return v if sign > 0 else b.neg(v)
         return [C(rot(x.re), rot(x.im)) for x in own]
 
@@ -640,6 +644,9 @@ LDS_F64 = 72
 # The four-lanes-per-event FP64 kernel runs two waves per compute unit: 80 KB of
 # LDS per wave, 160 doubles per lane.
 LDS_QUAD_F64 = 152
+# The two-lanes-per-event FP64 kernel runs one wave per SIMD with 80 doubles of
+# LDS per lane: 4 x 40 KB, the whole 160 KB of a compute unit.
+LDS_PAIR_F64 = 80
 # Shared quark-line products (Recursion.start_quark_line): 13% fewer flops for
 # gg -> ttbar gg.  The FP32 kernels run faster with them.  The FP64 kernel, whose
 # working set already spills, runs slower (the shared values add to the spill), so it
@@ -704,6 +711,14 @@ def emit_all(outdir, **opts):
                 f.write(f'__host__ __device__ constexpr double me_{name}_quad_norm_noalpha() '
                         f'{{ return 2.0 / ({proc.avg!r} * {float(proc.sym)!r} * {float(proc.cden)!r}); }}\n')
             flops['quad_executed_per_event'] = info_q['executed_per_event']
+            # two lanes per event (the default FP64 layout), in a file of its own
+            src_p, info_p = lane_split.emit_pair(proc, LDS_PAIR_F64, local_memo=True)
+            with open(os.path.join(outdir, f'me_{name}_pair.inc'), 'w') as f:
+                f.write('// Generated by paper_2211_14056_amd.gen.lane_split -- do not edit.\n')
+                f.write(src_p + '\n\n' + f'constexpr int me_{name}_pair_slots = {info_p["lds_slots"]};\n')
+                f.write(f'__host__ __device__ constexpr double me_{name}_pair_norm_noalpha() '
+                        f'{{ return 2.0 / ({proc.avg!r} * {float(proc.sym)!r} * {float(proc.cden)!r}); }}\n')
+            flops['pair_executed_per_event'] = info_p['executed_per_event']
         summary[name] = flops
     with open(os.path.join(outdir, 'flops.txt'), 'w') as f:
         for name, fl in summary.items():

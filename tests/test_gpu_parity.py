@@ -323,13 +323,54 @@ def test_me_empty_and_tiny_batches(h):
             assert np.abs(me.cpu().numpy() / ref - 1).max() < 1e-12
 
 
-def _quad_me(h, p):
-    """FP64 gg -> ttbar gg with the four-lanes-per-event layout."""
-    h.set_launch(mf.MF_GG_TTGG, mf.MF_FP64, 256)
+def _layout_me(h, p, block):
+    """FP64 gg -> ttbar gg with the event layout `block` selects (64: one lane per event,
+    128: two, 256: four); the handle goes back to its default (two lanes) afterwards."""
+    h.set_launch(mf.MF_GG_TTGG, mf.MF_FP64, block)
     try:
         return mf.matrix_element(h, mf.MF_GG_TTGG, p, mf.MF_FP64)
     finally:
-        h.set_launch(mf.MF_GG_TTGG, mf.MF_FP64, 64)
+        h.set_launch(mf.MF_GG_TTGG, mf.MF_FP64, 0)
+
+
+def _quad_me(h, p):
+    """FP64 gg -> ttbar gg with the four-lanes-per-event layout."""
+    return _layout_me(h, p, 256)
+
+
+@pytest.mark.parametrize('block,n', [(64, ME_N['gg_ttgg'] + 3), (128, 1), (128, 31), (128, 32), (128, 33),
+                                     (128, ME_N['gg_ttgg'] + 3)])
+def test_me_ttgg_layouts_vs_oracle(h, block, n):
+    """One lane per event and two lanes per event (orderings in pairs related by swapping the
+    beams and the final gluons, DPP exchange of currents and amplitudes) vs the oracle, with
+    batches that end inside a workgroup of 32 events."""
+    say('me ttgg layout', block, n)
+    ev = gpu_events(h, 'gg_ttgg', n, seed=32)
+    me = _layout_me(h, ev['p'], block)
+    torch.cuda.synchronize()
+    ref = oracle_me('gg_ttgg', ev['p'].cpu().numpy())
+    rel = np.abs(me.cpu().numpy() / ref - 1)
+    say('  max rel', rel.max())
+    assert rel.max() < 1e-12
+
+
+def test_me_ttgg_pair_layout_full_size(h):
+    """At the benchmark batch size the two-lane layout equals the one-lane kernel to rounding on
+    every event and sampled events match the oracle; an empty batch is a no-op."""
+    n = 1_000_000
+    say('me ttgg pair layout full size', n)
+    ev = gpu_events(h, 'gg_ttgg', n, seed=4)
+    a = _layout_me(h, ev['p'], 128)
+    b = _layout_me(h, ev['p'], 64)
+    torch.cuda.synchronize()
+    rel = ((a / b) - 1).abs()
+    say('  pair vs one-lane max rel', float(rel.max()))
+    assert float(rel.max()) < 1e-12
+    idx = np.concatenate([np.random.default_rng(5).choice(n, 16, replace=False), [0, 31, 32, n - 1]])
+    ref = oracle_me('gg_ttgg', ev['p'][:, :, torch.tensor(idx, device=a.device)].cpu().numpy())
+    assert np.abs(a[torch.tensor(idx, device=a.device)].cpu().numpy() / ref - 1).max() < 1e-12
+    e = _layout_me(h, torch.empty(6, 4, 0, dtype=torch.float64, device='cuda'), 128)
+    assert e.shape == (0,)
 
 
 @pytest.mark.parametrize('n', [1, 15, 16, 17, ME_N['gg_ttgg'] + 3])
@@ -353,7 +394,7 @@ def test_me_ttgg_quad_layout_full_size(h):
     say('me ttgg quad layout full size', n)
     ev = gpu_events(h, 'gg_ttgg', n, seed=4)
     a = _quad_me(h, ev['p'])
-    b = mf.matrix_element(h, mf.MF_GG_TTGG, ev['p'], mf.MF_FP64)
+    b = _layout_me(h, ev['p'], 64)
     torch.cuda.synchronize()
     rel = ((a / b) - 1).abs()
     say('  quad vs one-lane max rel', float(rel.max()))
