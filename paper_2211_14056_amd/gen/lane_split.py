@@ -275,7 +275,8 @@ def pair_shared_currents(k, need):
     return own, remote
 
 
-def emit_pair(proc, lds_budget, opaque_inputs=True, group_barriers=True, stream=True, local_memo=False):
+def emit_pair(proc, lds_budget, opaque_inputs=True, group_barriers=True, stream=True, local_memo=False,
+              share_products=False):
     """Source text and flop counts of me_<name>_pair (two lanes per event)."""
     k = proc.k
     assert k == 4, 'the pair split is laid out for four gluons'
@@ -361,7 +362,7 @@ def emit_pair(proc, lds_budget, opaque_inputs=True, group_barriers=True, stream=
             qmoms.append(Momentum(q, [S(name=f'K{j}[0]'), ZERO, ZERO, S(name=f'K{j}[3]')]))
         else:
             qmoms.append(Momentum(q, [S(name=f'K{j}[{c}]') for c in range(4)]))
-    rec.start_quark_line(q, qmoms, ub)
+    rec.start_quark_line(q, qmoms, ub, mine, share_products)
     vspin = [[C(S(name=f'vs[{h}][{j}].re'), S(name=f'vs[{h}][{j}].im')) for j in range(4)] for h in range(2)]
     amps = [[None] * len(mine) for _ in range(2)]
     prev = None
