@@ -1,5 +1,5 @@
 // g g -> t tbar g g with four lanes per event (lanes 4j..4j+3 of a wave share
-// event j), used for the FP64 kernel.  With one lane per event the FP64
+// event j), an option for the FP64 kernel.  With one lane per event the FP64
 // working set (24 partial amplitudes and 34 multi-gluon currents per helicity
 // configuration) is about twice the register file and spills to memory.  The
 // quad form divides the colour orderings by their first gluon.  Each lane
