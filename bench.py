@@ -11,15 +11,17 @@ path matches the FP64 CPU oracle to 1e-12 in the parity tests).
 
 By default the batches are pipelined over two HIP streams: the phase space of
 batch i+1 runs beside the matrix element of batch i (`--streams 1` serialises
-them).  The matrix elements stay on one stream, one at a time, so the HIP events
-around each matrix-element launch time that kernel alone; the roofline figures
-come from those launch durations, the headline from the wall clock of the steps.
+them; `--streams 3` also moves the Vegas calls to a third stream, which measured
+no faster).  The matrix elements stay on one stream, one at a time, so the HIP
+events around each matrix-element launch time that kernel alone; the roofline
+figures come from those launch durations, the headline from the wall clock of
+the steps.
 
 Beside the headline the JSON line carries `extras`: the derivative (VJP) on the
 gg -> ttbar g configuration (4e6 events, FP32 and FP64) and the 64-request mixed
 batch, one persistent launch against one launch per request.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp32_mfma_f32] [--no-extras] [--streams 1|2]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp32_mfma_f32] [--no-extras] [--streams 1|2|3]
 """
 import argparse
 import json
@@ -94,11 +96,11 @@ def flops_per_event(proc, precision_name):
 def enqueue_order(first, count, streams):
     """[(op, batch)] in the order the batches first..first+count-1 are enqueued.
 
-    op 'ps' is the phase space of the batch, op 'rest' its matrix element and Vegas
-    call.  With two buffers the phase space of i+1 is enqueued before the rest of i,
-    except where i+1 opens a Vegas iteration: its phase space needs the grid that
-    batch i's refine writes, so it comes after that refine.  With one buffer it
-    always comes after the rest of i, which still reads the buffer."""
+    op 'ps' is the phase space of the batch, 'me' its matrix element and 'vg' its
+    Vegas call.  With two buffers (streams >= 2) the phase space of i+1 is enqueued
+    before the matrix element of i, except where i+1 opens a Vegas iteration: its
+    phase space needs the grid that batch i's refine writes, so it comes after that
+    refine.  With one buffer it always comes after batch i, which still reads it."""
     order = [('ps', first)]
     for k in range(count):
         i = first + k
@@ -106,7 +108,7 @@ def enqueue_order(first, count, streams):
         if nxt and streams > 1 and (i + 1) % BATCHES_PER_ITER != 0:
             order.append(('ps', i + 1))
             nxt = False
-        order.append(('rest', i))
+        order += [('me', i), ('vg', i)]
         if nxt:
             order.append(('ps', i + 1))
     return order
@@ -115,14 +117,19 @@ def enqueue_order(first, count, streams):
 def run_path(mf, h, prm, precision, steps, warmup, seed, streams=2):
     """Time `steps` batches of the full forward path; returns timings and the last batch's ME.
 
-    streams = 2: the phase space of batch i+1 runs on a second HIP stream, into the second
+    streams >= 2: the phase space of batch i+1 runs on a second HIP stream, into the second
     of two event buffers, while the matrix element of batch i runs.  Its waves take the
     compute units that batch i's last matrix-element waves leave idle: 1e6 events are 15.3
-    waves per SIMD.  The matrix elements and the Vegas calls stay on one stream, in batch
-    order, so no two matrix-element launches overlap and each launch's HIP events time that
-    kernel alone.  Events order the two streams:
-      * a buffer is refilled only after the Vegas call that last read it;
+    waves per SIMD.  streams = 3: the Vegas calls run on a third stream, so the matrix
+    element of batch i+1 need not wait for the Vegas call of batch i.  The matrix elements
+    stay on one stream, in batch order, so no two matrix-element launches overlap and each
+    launch's HIP events time that kernel alone; the Vegas calls, too, stay in batch order
+    on one stream.  Events order the streams:
       * a matrix element starts only when its phase space is done;
+      * a Vegas call starts only when its matrix element is done;
+      * a buffer is refilled only after the Vegas call that last read it (and so after
+        its matrix element), so a later matrix element cannot overwrite a result that
+        is still to be read;
       * the first batch of a Vegas iteration waits for the grid refined by the previous one.
     streams = 1: everything on one stream.
     """
@@ -132,26 +139,29 @@ def run_path(mf, h, prm, precision, steps, warmup, seed, streams=2):
     f64 = dict(dtype=torch.float64, device=dev)
     edges = torch.tensor(np.tile(np.linspace(0, 1, NB + 1), (d, 1)), **f64).contiguous()
     acc = torch.zeros(2 + d * NB, **f64)
+    nbuf = 1 if streams == 1 else 2
     bufs = []
-    for _ in range(streams):
+    for _ in range(nbuf):
         b = dict(p=torch.empty(6, 4, BATCH, **f64), w=torch.empty(BATCH, **f64), jac=torch.empty(BATCH, **f64),
                  pas=torch.empty(BATCH, dtype=torch.uint8, device=dev),
                  bins=torch.empty(d, BATCH, dtype=torch.int16, device=dev),
                  me=torch.empty(BATCH, dtype=torch.float64 if precision == mf.MF_FP64 else torch.float32,
                                 device=dev))
         b['req'] = [mf.make_request(pid, b['p'], b['me'])]
-        b['free'] = torch.cuda.Event()        # recorded after the Vegas call that read the buffer
         b['ready'] = torch.cuda.Event()       # recorded after the phase space that filled it
+        b['computed'] = torch.cuda.Event()    # recorded after the matrix element that filled `me`
+        b['free'] = torch.cuda.Event()        # recorded after the Vegas call that read the buffer
         bufs.append(b)
-    main = torch.cuda.Stream()                # default priority
-    side = torch.cuda.Stream() if streams == 2 else main
+    main = torch.cuda.Stream()                # default priority (all three)
+    side = torch.cuda.Stream() if streams >= 2 else main
+    vstream = torch.cuda.Stream() if streams == 3 else main
     grid_done = torch.cuda.Event()
     # HIP events around every matrix-element launch of the timed region, recorded on
     # the stream the library launches it on; read after the end
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
 
     def phase_space(i):
-        b = bufs[i % streams]
+        b = bufs[i % nbuf]
         with torch.cuda.stream(side):
             side.wait_event(b['free'])
             if i % BATCHES_PER_ITER == 0:
@@ -160,8 +170,8 @@ def run_path(mf, h, prm, precision, steps, warmup, seed, streams=2):
                               w=b['w'], pass_=b['pas'], bin_idx=b['bins'], jac=b['jac'])
             b['ready'].record(side)
 
-    def rest(i, ev=None):
-        b = bufs[i % streams]
+    def matrix_element(i, ev=None):
+        b = bufs[i % nbuf]
         with torch.cuda.stream(main):
             main.wait_event(b['ready'])
             if ev:
@@ -169,19 +179,27 @@ def run_path(mf, h, prm, precision, steps, warmup, seed, streams=2):
             mf.mf_matrix_element(h, b['req'], precision, prm)
             if ev:
                 ev[1].record(main)
+            b['computed'].record(main)
+
+    def vegas(i):
+        b = bufs[i % nbuf]
+        with torch.cuda.stream(vstream):
+            vstream.wait_event(b['computed'])
             last = (i + 1) % BATCHES_PER_ITER == 0
             mf.mf_vegas_refine(h, prm, BATCH, d, NB, 1.5, b['w'], b['jac'], b['me'], b['pas'], b['bins'], acc,
                                edges, update_edges=last, accumulate=(i % BATCHES_PER_ITER) != 0)
-            b['free'].record(main)
+            b['free'].record(vstream)
             if last:
-                grid_done.record(main)
+                grid_done.record(vstream)
 
     def run(first, count, timed):
         for op, i in enqueue_order(first, count, streams):
             if op == 'ps':
                 phase_space(i)
+            elif op == 'me':
+                matrix_element(i, evs[i - first] if timed else None)
             else:
-                rest(i, evs[i - first] if timed else None)
+                vegas(i)
 
     torch.cuda.synchronize()
     if warmup:
@@ -192,7 +210,7 @@ def run_path(mf, h, prm, precision, steps, warmup, seed, streams=2):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     me_ms = [a.elapsed_time(b) for a, b in evs]
-    lb = bufs[(warmup + steps - 1) % streams]
+    lb = bufs[(warmup + steps - 1) % nbuf]
     return dict(seconds=t1 - t0, me_ms=float(np.mean(me_ms)), me=lb['me'], pas=lb['pas'], p=lb['p'], acc=acc,
                 edges=edges)
 
@@ -290,8 +308,9 @@ def main():
     ap.add_argument('--precision', default='auto')
     ap.add_argument('--no-cpu-baseline', action='store_true')
     ap.add_argument('--no-extras', action='store_true', help='skip the derivative and mixed-batch timings')
-    ap.add_argument('--streams', type=int, default=2, choices=(1, 2),
-                    help='2: the next batch\'s phase space runs on a second stream beside the matrix element')
+    ap.add_argument('--streams', type=int, default=2, choices=(1, 2, 3),
+                    help='2: the next batch\'s phase space runs on a second stream beside the matrix element; '
+                         '3: the Vegas calls run on a third stream')
     ap.add_argument('--seed', type=int, default=4)
     ap.add_argument('--copy-calibration', action='store_true',
                     help=f'also run one {COPY_BYTES >> 20} MiB device-to-device copy (counter calibration)')

@@ -67,7 +67,7 @@ def test_pipelined_schedules_match_sequential_calls(h, precision):
     steps, warmup = 18, 1
     print(f'[gpu-test] bench schedule {precision}: sequential reference', flush=True)
     ref = sequential(h, prm, prec, warmup + steps - 1, seed=7)
-    for streams in (1, 2):
+    for streams in (1, 2, 3):
         print(f'[gpu-test] bench schedule {precision}: streams {streams}', flush=True)
         got = bench.run_path(mf, h, prm, prec, steps, warmup, seed=7, streams=streams)
         torch.cuda.synchronize()
