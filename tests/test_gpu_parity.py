@@ -761,6 +761,29 @@ def test_graph_vegas_gg_tt_cross_section(h):
     assert abs(I - ref) < 3 * sig
 
 
+def test_vegas_gg_ttgg_fp32_matrix_core_matches_fp64(h):
+    """The whole Vegas path for gg -> ttbar gg at the benchmark's scale (three iterations of 4 x 10^6
+    events, the grid refined after each) with FP32 amplitudes and BF16x3 matrix-core colour, against the
+    FP64 path on the same uniforms.  Per-event differences of about 1e-7 must leave every iteration's
+    integral and the refined grid equal to far inside the Monte Carlo error (a cut decision that flips at
+    rounding level moves one event, which that margin covers)."""
+    from paper_2211_14056_amd.integrator import VegasIntegrator
+    res = {}
+    for prec in (mf.MF_FP64, mf.MF_FP32_MFMA_BF16):
+        say('vegas gg_ttgg, precision', prec)
+        vi = VegasIntegrator('gg_ttgg', precision=prec, n=1_000_000, batches=4, seed=9, handle=h)
+        per_iter = vi.iterate(3)
+        res[prec] = (per_iter, vi.estimate(), vi.edges.clone())
+    (it64, (I64, s64, _), e64), (it32, (I32, s32, _), e32) = res[mf.MF_FP64], res[mf.MF_FP32_MFMA_BF16]
+    say('  sigma fp64', I64, '+-', s64, ' fp32+mfma', I32, '+-', s32)
+    assert I64 > 0 and s64 < 0.05 * I64
+    for (a, va), (b, vb) in zip(it64, it32):
+        assert abs(a - b) < 0.05 * math.sqrt(va)
+        assert abs(vb / va - 1) < 1e-3
+    assert abs(I32 - I64) < 0.05 * s64
+    assert float((e32 - e64).abs().max()) < 1e-4
+
+
 def test_autotuner(h, tmp_path, monkeypatch):
     from paper_2211_14056_amd import autotune
     monkeypatch.setenv('MF_TUNE_CACHE', str(tmp_path / 'tune.json'))
