@@ -784,6 +784,22 @@ def test_vegas_gg_ttgg_fp32_matrix_core_matches_fp64(h):
     assert float((e32 - e64).abs().max()) < 1e-4
 
 
+def test_autotune_report(h):
+    """The sweep report (python -m paper_2211_14056_amd.autotune --report) measures every table and
+    leaves the handle on its defaults, so later launches give the same numbers as before it."""
+    from paper_2211_14056_amd import autotune
+    say('autotune report')
+    ev = gpu_events(h, 'gg_ttgg', 300, seed=8)
+    before = mf.matrix_element(h, mf.MF_GG_TTGG, ev['p'], mf.MF_FP64)
+    text = autotune.report(h, sizes=(1 << 12,))
+    for head in ('## Block size', '## Event layout', '## Persistent mixed batch'):
+        assert head in text
+    assert text.count('| gg_tt |') == 3 and text.count('| gg_ttg |') == 3
+    after = mf.matrix_element(h, mf.MF_GG_TTGG, ev['p'], mf.MF_FP64)
+    torch.cuda.synchronize()
+    assert torch.equal(before, after)
+
+
 def test_autotuner(h, tmp_path, monkeypatch):
     from paper_2211_14056_amd import autotune
     monkeypatch.setenv('MF_TUNE_CACHE', str(tmp_path / 'tune.json'))
