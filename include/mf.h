@@ -72,6 +72,10 @@ typedef struct {
 } mf_params;
 
 /* One batch of events of one process.
+ *   proc       an mf_process; reserved: set to 0;
+ *   n          number of events (0 is a no-op);
+ *   p          [n_ext][4][n] f64 momenta, layout as above (forward only; the
+ *              derivative regenerates the momenta from x);
  *   me_out     [n] f64 (MF_FP64) or f32 (other precisions): spin- and colour-
  *              summed |M|^2 averaged over initial helicities/colours, including
  *              the 1/2 for identical final gluons.
