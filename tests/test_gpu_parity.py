@@ -564,7 +564,7 @@ def test_vjp_fp64_vs_oracle_reverse_mode(h, proc):
     assert np.abs(gth[:, 1] / gth_o[:, 1] - 1).max() < 1e-12
 
 
-@pytest.mark.parametrize('proc', ['gg_tt', 'gg_ttg'])
+@pytest.mark.parametrize('proc', ['gg_tt', 'gg_ttg', 'gg_ttgg'])
 def test_vjp_fp32_vs_oracle(h, proc):
     from oracle import grad as ograd
     n = VJP_N[proc]
@@ -579,6 +579,30 @@ def test_vjp_fp32_vs_oracle(h, proc):
     err = _normwise(ga, gb)
     say('  median', np.median(err), 'max', err.max())
     assert np.median(err) < 1e-4 and err.max() < 1e-2
+
+
+@pytest.mark.parametrize('precision', ['fp64', 'fp32'])
+def test_vjp_empty_and_tiny_batches(h, precision):
+    """n = 0 is a no-op; one event and a ragged 65 (one full wavefront plus one) match the oracle."""
+    from oracle import grad as ograd
+    prec = mf.PRECISION[precision]
+    for proc, n in (('gg_tt', 0), ('gg_ttg', 0), ('gg_tt', 1), ('gg_ttg', 1), ('gg_tt', 65)):
+        say('vjp tiny batch', precision, proc, n)
+        d = processes.dims(proc)
+        x = philox.uniforms(44, n, d)
+        gbar = np.linspace(0.5, 1.5, n)
+        me, gx, gth = _vjp_gpu(h, proc, x, gbar, prec)
+        assert me.shape == (n,) and gx.shape == (d, n) and gth.shape == (n, 2)
+        if not n:
+            continue
+        me_o, gx_o, gth_o = ograd.vjp(proc, P, x, gbar)
+        err = _normwise(np.concatenate([gx, gth[:, :1].T], 0), np.concatenate([gx_o, gth_o[:, :1].T], 0))
+        if precision == 'fp64':
+            assert np.abs(me / me_o - 1).max() < 1e-12
+            assert err.max() < 1e-10
+        else:
+            assert np.abs(me / me_o - 1).max() < 1e-3
+            assert np.median(err) < 1e-4 and err.max() < 1e-2
 
 
 def test_vjp_vs_finite_differences_ttg(h):
