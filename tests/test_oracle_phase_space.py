@@ -99,6 +99,32 @@ def test_massless_isotropy_every_particle(n):
         assert abs((c[:, i] ** 2).mean() - 1 / 3) < 5 * math.sqrt(4 / 45 / N)
 
 
+def test_massless_three_body_dalitz_plot_is_flat():
+    """With a constant weight, massless three-body events fill the Dalitz triangle
+    x1 + x2 >= 1, x1, x2 <= 1 (x_i = 2E_i/sqrt(s), equivalently s23 = s(1 - x1),
+    s13 = s(1 - x2)) uniformly: the three-body phase-space density is flat in two
+    invariant masses.  Checked by a chi-square over the 45 cells of a 10 x 10 grid
+    that lie wholly inside the triangle, and by the fraction on the diagonal cells."""
+    N = 200000
+    p, w = _sample(3, N, 41)
+    assert float(w.std()) <= 1e-12 * float(w.mean())
+    x = (2 * p[..., 0] / SQRT_S).numpy()
+    x1, x2 = x[:, 0], x[:, 1]
+    assert (x1 + x2 >= 1 - 1e-12).all() and (x1 <= 1 + 1e-12).all() and (x2 <= 1 + 1e-12).all()
+    i = np.minimum((x1 * 10).astype(int), 9)
+    j = np.minimum((x2 * 10).astype(int), 9)
+    counts = np.zeros((10, 10))
+    np.add.at(counts, (i, j), 1)
+    full = np.add.outer(np.arange(10), np.arange(10)) >= 10
+    expect = N * 0.01 / 0.5
+    chi2 = float((((counts[full] - expect) ** 2) / expect).sum())
+    assert full.sum() == 45 and chi2 < 45 + 5 * math.sqrt(2 * 45), chi2
+    # the 10 cells the diagonal cuts hold half a full cell's area each
+    diag = np.add.outer(np.arange(10), np.arange(10)) == 9
+    frac = counts[diag].sum() / N
+    assert abs(frac - 0.1) < 5 * math.sqrt(0.1 * 0.9 / N), frac
+
+
 def test_diet_matches_classic_rambo_pair_invariants():
     n, N = 4, 200000
     p, _ = _sample(n, N, 31)
