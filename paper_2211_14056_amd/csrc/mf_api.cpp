@@ -69,7 +69,10 @@ mf_status ensure_partials(mf_handle h, size_t need)
 {
     if (h->partials_cap >= need) return MF_OK;
     if (h->partials) {
-        hipDeviceSynchronize();
+        // launches already enqueued may still read the old workspace; an error they
+        // left is reported here rather than dropped
+        hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess) return hip_fail(e, "mf_vegas_refine: hipDeviceSynchronize");
         hipFree(h->partials);
         h->partials = nullptr;
         h->partials_cap = 0;
