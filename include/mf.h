@@ -81,6 +81,7 @@ typedef struct {
  *              the 1/2 for identical final gluons.
  * VJP only:
  *   x          [d][n] f64 uniforms that generated the event (d = 3 n_out - 4),
+ *              binned as in mf_phase_space (outside [0, 1): first or last bin),
  *   grad_me    [n] f64 incoming cotangent g,
  *   grad_x     [d][n] f64 out: g * d|M|^2/dx (through the Vegas map and phase space),
  *   grad_theta [n][2] f64 out: g * (d|M|^2/dm_t at fixed x, d|M|^2/dalpha_s). */
@@ -143,6 +144,9 @@ mf_status mf_failures(mf_handle h, uint64_t* count);
  * rescaling, generation cuts.
  *   x          [d][n] uniforms, or NULL to draw them from Philox4x32-10 with
  *              key = seed and counter = (offset + *offset_dev + event, dim/2);
+ *              a value outside [0, 1) falls in the first or last Vegas bin
+ *              (the map extrapolates linearly) and NaN in bin 0 with NaN
+ *              momenta, so no caller value makes an edge read go out of bounds;
  *   offset_dev optional device pointer added to offset (lets a captured graph
  *              advance the stream between replays), may be NULL;
  *   edges      [d][nb+1] Vegas grid, or NULL for the identity map;

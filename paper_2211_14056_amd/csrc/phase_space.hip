@@ -48,8 +48,7 @@ __global__ __launch_bounds__(256) void k_phase_space(PsArgs a)
 #pragma unroll
         for (int k = 0; k < D; ++k) {
             const double t = x[k] * nb;
-            int i = (int)floor(t);
-            i = i > nb - 1 ? nb - 1 : i;
+            const int i = vegas_bin(t, nb);
             const double* ed = a.edges + k * (nb + 1);
             const double lo = ed[i], wdt = ed[i + 1] - lo;
             y[k] = lo + (t - i) * wdt;
@@ -61,8 +60,7 @@ __global__ __launch_bounds__(256) void k_phase_space(PsArgs a)
         for (int k = 0; k < D; ++k) {
             y[k] = x[k];
             if (a.bin_idx) {
-                int i = (int)floor(x[k] * a.nb);
-                a.bin_idx[k * n + e] = (int16_t)(i > a.nb - 1 ? a.nb - 1 : i);
+                a.bin_idx[k * n + e] = (int16_t)vegas_bin(x[k] * a.nb, a.nb);
             }
         }
     }

@@ -64,12 +64,19 @@ __device__ inline double solve_mass_ratio_sq(double u, int a)
 }
 
 // Vegas map of one uniform: y = e_i + (x nb - i)(e_{i+1} - e_i); returns the bin.
+// The bin is clamped to [0, nb) before any edge is read, so a uniform outside
+// [0, 1) uses the first or last bin (extrapolated linearly) and a NaN uniform
+// bin 0 with y = NaN: the edge reads stay in bounds whatever the caller passes.
+__device__ __forceinline__ int vegas_bin(double t, int nb)
+{
+    return (int)fmin(fmax(floor(t), 0.0), double(nb - 1));    // fmax drops a NaN
+}
+
 template <typename KT>
 __device__ __forceinline__ int vegas_map1(KT x, const double* ed, int nb, KT& y, double& jac)
 {
     const KT t = x * double(nb);
-    int i = (int)floor(kval(t));
-    i = i > nb - 1 ? nb - 1 : i;
+    const int i = vegas_bin(kval(t), nb);
     const double lo = ed[i], wdt = ed[i + 1] - lo;
     y = (t - double(i)) * wdt + lo;
     jac *= nb * wdt;

@@ -135,6 +135,68 @@ def test_phase_space_conservation_full_size(h):
     assert h.failures() == 0
 
 
+def _bad_uniforms(x, nb):
+    """Copy of x with a NaN, a negative and a >= 1 uniform in three events; returns
+    (x_bad, {event: (dim, expected bin)})."""
+    xb = x.copy()
+    bad = {5: (0, 0), 70: (1, 0), x.shape[1] - 1: (2, nb - 1)}
+    for e, (k, _) in bad.items():
+        xb[k, e] = (np.nan, -0.25, 1.25)[list(bad).index(e)]
+    return xb, bad
+
+
+def test_phase_space_out_of_range_uniforms_stay_in_bounds(h):
+    """Caller uniforms outside [0, 1) or NaN: the Vegas bins are clamped (first or last
+    bin, NaN in bin 0), and every other event is bit-identical to a run without them,
+    in the phase space and in the derivative."""
+    proc, n, nb = 'gg_ttg', 130, 50
+    pid, d = mf.PROCESS[proc], processes.dims(proc)
+    x = philox.uniforms(50, n, d)
+    xb, bad = _bad_uniforms(x, nb)
+    keep = np.setdiff1d(np.arange(n), list(bad))
+    ed = _edges(d, 3)
+    dev = torch.device('cuda', 0)
+    e = torch.tensor(ed, dtype=torch.float64, device=dev).contiguous()
+    hh = mf.Handle(0)                      # own handle: the NaN event is counted as a failure
+    try:
+        outs = []
+        for xx in (x, xb):
+            say('phase space with caller uniforms', proc, n, 'bad' if xx is xb else 'good')
+            xt = torch.tensor(xx, dtype=torch.float64, device=dev).contiguous()
+            o = mf.mf_phase_space(hh, pid, prm_of(proc), n, x=xt, edges=e, nb=nb,
+                                  pass_=torch.empty(n, dtype=torch.uint8, device=dev),
+                                  bin_idx=torch.empty(d, n, dtype=torch.int16, device=dev),
+                                  jac=torch.empty(n, dtype=torch.float64, device=dev))
+            torch.cuda.synchronize()
+            outs.append({k: v.cpu().numpy() for k, v in o.items() if k != 'x'})
+        good, got = outs
+        b = got['bin_idx']
+        assert b.min() >= 0 and b.max() <= nb - 1
+        for ev, (k, want) in bad.items():
+            assert b[k, ev] == want, (ev, k, b[k, ev])
+        assert np.isnan(got['p'][2:, :, 5]).any()
+        for k in ('p', 'w', 'jac', 'pass_', 'bin_idx'):
+            assert np.array_equal(got[k][..., keep], good[k][..., keep]), k
+        # the clamped events' Jacobian is the product of their bins' widths
+        for ev in list(bad)[1:]:
+            jac = 1.0
+            for k in range(d):
+                i = b[k, ev]
+                jac *= nb * (ed[k, i + 1] - ed[k, i])
+            assert abs(got['jac'][ev] / jac - 1) < 1e-14
+        # the derivative maps x the same way
+        gb = np.ones(n)
+        for prec in (mf.MF_FP64, mf.MF_FP32):
+            say('vjp with caller uniforms', proc, n, prec)
+            me_r, gx_r, gth_r = _vjp_gpu(hh, proc, x, gb, prec, edges=ed)
+            me_b, gx_b, gth_b = _vjp_gpu(hh, proc, xb, gb, prec, edges=ed)
+            assert np.array_equal(me_b[keep], me_r[keep])
+            assert np.array_equal(gx_b[:, keep], gx_r[:, keep])
+            assert np.array_equal(gth_b[keep], gth_r[keep])
+    finally:
+        hh.close()
+
+
 # ------------------------------------------------------------------ matrix element
 ME_N = {'ee_mumu': 2000, 'gg_tt': 2000, 'gg_ttg': 300, 'gg_ttgg': 40}
 
