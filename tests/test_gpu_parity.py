@@ -260,6 +260,32 @@ def test_me_mfma_colour_vs_oracle(h, proc, prec):
     assert np.median(rel) < 1e-5 and rel.max() < 1e-3
 
 
+NAN_FORMS = ([(proc, 'fp64') for proc in PROCS] + [(proc, 'fp32') for proc in PROCS]
+             + [(proc, prec) for proc in PROCS[1:] for prec in ('fp32_mfma_f32', 'fp32_mfma_bf16')])
+
+
+@pytest.mark.parametrize('proc,prec', NAN_FORMS)
+def test_me_nan_momenta_give_nan_and_leave_other_events(h, proc, prec):
+    """NaN momenta in one event give a NaN |M|^2 for that event; every other event of
+    the launch (same wavefront, same matrix-core tile) is bit-identical to a clean run."""
+    n, bad = 130, 7
+    say('me nan event', proc, prec, n)
+    ev = gpu_events(h, proc, n, seed=24)
+    p = ev['p'].contiguous()
+    pb = p.clone()
+    pb[2, :, bad] = float('nan')
+    keep = np.arange(n) != bad
+    blocks = [64, 128, 256] if (proc, prec) == ('gg_ttgg', 'fp64') else [None]
+    for blk in blocks:
+        if blk is None:
+            a, b = gpu_me(h, proc, p, mf.PRECISION[prec]), gpu_me(h, proc, pb, mf.PRECISION[prec])
+        else:
+            a = _layout_me(h, p, blk).cpu().numpy()
+            b = _layout_me(h, pb, blk).cpu().numpy()
+        assert np.isnan(b[bad]), (blk, b[bad])
+        assert np.array_equal(a[keep], b[keep]), blk
+
+
 @pytest.mark.parametrize('n', [1, 63, 65, 257])
 def test_me_mfma_ragged_batches(h, n):
     say('mfma ragged', n)
