@@ -316,7 +316,7 @@ def main():
                     help=f'also run one {COPY_BYTES >> 20} MiB device-to-device copy (counter calibration)')
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f'bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); '
+        print(f'bench.py: the library runs on one GPU only (asked for --gpus {args.gpus}); '
               'the event axis would shard across GPUs with one all-reduce of the Vegas '
               'accumulators per iteration, which is not built here.', file=sys.stderr)
         sys.exit(2)

@@ -40,7 +40,7 @@ extern "C" {
 typedef enum {
     MF_OK = 0,
     MF_ERR_INVALID_ARG = -1,  /* null pointer, negative size, unknown enum, ... */
-    MF_ERR_UNSUPPORTED = -2,  /* valid request this build cannot serve */
+    MF_ERR_UNSUPPORTED = -2,  /* valid request the library cannot serve */
     MF_ERR_HIP = -3,          /* HIP runtime error (message has the HIP error string) */
     MF_ERR_NO_MEMORY = -4     /* workspace allocation failed */
 } mf_status;
@@ -213,7 +213,7 @@ mf_status mf_vegas_refine(mf_handle h, const mf_params* prm, int64_t n, int d, i
                           const uint8_t* pass, const int16_t* bin_idx, double* F, double* acc,
                           double* edges, int flags, uint64_t* rng_counter, void* stream);
 
-/* 1 if this build serves matrix elements at `precision`, else 0. */
+/* 1 if the library serves matrix elements at `precision`, else 0. */
 int mf_precision_available(int precision);
 
 #ifdef __cplusplus
