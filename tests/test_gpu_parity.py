@@ -785,6 +785,32 @@ def _mixed_requests(h, spec, precision, seed0=200):
     return reqs, outs, evs
 
 
+@pytest.mark.parametrize('prec', ['fp64', 'fp32_mfma_bf16'])
+def test_persistent_batch_nan_event_stays_in_its_request(h, prec):
+    """One persistent launch over mixed requests: NaN momenta in the ragged tail of one
+    request give NaN there and leave every other result of every request bit-identical."""
+    from paper_2211_14056_amd.workloads import mixed_batch
+    spec = mixed_batch(12, seed=5, scale=0.004)
+    spec[0] = ('gg_ttgg', 1)
+    spec[1] = ('gg_tt', 65)
+    say('persistent batch nan event', prec, spec)
+    P_ = mf.PRECISION[prec]
+    reqs, outs, evs = _mixed_requests(h, spec, P_)
+    mf.mf_matrix_element(h, reqs, P_, mf.params())
+    torch.cuda.synchronize()
+    clean = [o.double().cpu().numpy() for o in outs]
+    evs[1]['p'][2, :, 64] = float('nan')          # the request's buffers are the events' tensors
+    torch.cuda.synchronize()
+    mf.mf_matrix_element(h, reqs, P_, mf.params())
+    torch.cuda.synchronize()
+    got = [o.double().cpu().numpy() for o in outs]
+    assert np.isnan(got[1][64])
+    assert np.array_equal(got[1][:64], clean[1][:64])
+    for i in range(len(spec)):
+        if i != 1:
+            assert np.array_equal(got[i], clean[i]), (i, spec[i])
+
+
 @pytest.mark.parametrize('prec', ['fp64', 'fp32', 'fp32_mfma_f32', 'fp32_mfma_bf16'])
 def test_persistent_batch_equals_separate_launches(h, prec):
     from paper_2211_14056_amd.workloads import mixed_batch
