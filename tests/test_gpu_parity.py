@@ -597,6 +597,9 @@ def test_vegas_pull_distribution(h):
         say('vegas pulls', proc, 'mean', pulls.mean(), 'std', pulls.std(ddof=1))
         assert abs(pulls.mean()) < 3 / math.sqrt(20)
         assert 0.5 < pulls.std(ddof=1) < 1.5
+        # "within 1 sigma" over seeds: I +- sigma covers the closed form at the nominal 68% rate
+        # (binomial(20, 0.683): mean 13.7, standard deviation 2.1)
+        assert (np.abs(pulls) < 1).sum() >= 8
 
 
 # ------------------------------------------------------------------ derivative

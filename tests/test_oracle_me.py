@@ -271,6 +271,24 @@ def test_gg_tt_cross_section_within_sigma():
     assert abs(I - ref) < 3 * sig
 
 
+def test_ee_mumu_one_sigma_coverage_over_seeds():
+    """"Within 1 Monte Carlo sigma", read over seeds: the interval I +- sigma covers the closed
+    form at the nominal 68% rate, and the pulls (I - sigma_ref)/sigma have mean 0 and spread 1,
+    each within its 3-sigma sampling range for 20 draws.  A single seed is within 1 sigma only
+    with probability 0.68, so the per-seed checks above use 3 sigma."""
+    ref = closed_forms.ee_mumu_sigma(PEE['sqrt_s'] ** 2, PEE['alpha']) * closed_forms.GEV2_TO_PB
+    f = lambda y: integrand.integrand('ee_mumu', PEE, y)[0]
+    pulls = []
+    for seed in range(1, 21):
+        I, sig, chi2, _, _ = vegas.integrate(f, 2, 5000, 4, seed=200 + seed)
+        pulls.append((I - ref) / sig)
+    pulls = np.array(pulls)
+    assert abs(pulls.mean()) < 3 / math.sqrt(20)
+    assert 0.5 < pulls.std(ddof=1) < 1.5
+    # binomial(20, 0.683): mean 13.7, standard deviation 2.1
+    assert (np.abs(pulls) < 1).sum() >= 8
+
+
 def test_gg_tt_sigma_closed_form_vs_quadrature_of_me():
     # the two published forms pin each other: integrate the per-event formula over cos theta
     from scipy import integrate as si
