@@ -17,6 +17,11 @@ events around each matrix-element launch time that kernel alone; the roofline
 figures come from those launch durations, the headline from the wall clock of
 the steps.
 
+The run publishes no throughput (exit status 3) unless the FP32 results meet their bars
+(median 1e-5, max 1e-3 relative, no NaN) against FP64 on every event of the last batch that
+passes the cuts and against the FP64 CPU oracle on the cpu_baseline sample, and FP64 meets
+1e-12 against the oracle there.
+
 Beside the headline the JSON line carries `extras`: the derivative (VJP) on the
 gg -> ttbar g configuration (4e6 events, FP32 and FP64) and the 64-request mixed
 batch, one persistent launch against one launch per request.
@@ -274,30 +279,116 @@ def extras(mf, h, prm, seed):
     return out
 
 
-def cpu_baseline(seed, budget_s=45.0):
-    """The FP64 oracle (colour-ordered mode) on the host cores, bounded sample."""
-    from oracle import integrand, philox, processes, vegas as ovegas
-    torch.set_num_threads(os.cpu_count() or 1)
-    par = processes.DEFAULT_PARAMS
-    d = processes.dims(PROC)
-    n = 256
-    # warm-up and size the sample from it (the small warm-up sample costs more
-    # per event, so the timed sample lands at roughly 10-30 s)
-    x = philox.uniforms(seed, n, d)
-    t0 = time.perf_counter()
-    integrand.integrand(PROC, par, x)
-    dt = time.perf_counter() - t0
-    n = int(max(256, min(20000, n * budget_s / max(dt, 1e-3))))
-    x = philox.uniforms(seed, n, d)
-    edges = ovegas.uniform_grid(d, NB)
+def _cpu_model():
+    try:
+        for line in open('/proc/cpuinfo'):
+            if line.startswith('model name'):
+                return line.split(':', 1)[1].strip()
+    except OSError:
+        pass
+    return 'unknown'
+
+
+def _host_threads():
+    """Threads the host share allows: the affinity mask, capped by OMP_NUM_THREADS when set."""
+    n = len(os.sched_getaffinity(0)) if hasattr(os, 'sched_getaffinity') else (os.cpu_count() or 1)
+    try:
+        n = min(n, int(os.environ.get('OMP_NUM_THREADS', n)))
+    except ValueError:
+        pass
+    return max(1, n)
+
+
+def _oracle_pass(proc, par, x, edges):
+    """One pass of the oracle over the uniforms x [d][n]: Vegas map, phase space, cuts,
+    colour-ordered FP64 |M|^2, Vegas accumulation.  Returns (seconds, |M|^2, pass mask)."""
+    from oracle import integrand, vegas as ovegas
     t0 = time.perf_counter()
     y, b, J = ovegas.vegas_map(x, edges)
-    F, ok, me = integrand.integrand(PROC, par, y)
+    F, ok, me = integrand.integrand(proc, par, y)
     ovegas.accumulate(F * J, b, NB)
-    dt = time.perf_counter() - t0
-    return dict(value=n / dt, unit='events/s', cores=torch.get_num_threads(), kind='oracle',
-                sample=f'{n} gg->ttbar gg events (uniforms, Vegas map, phase space, cuts, '
-                       f'colour-ordered FP64 |M|^2, Vegas accumulation) in {dt:.1f} s')
+    return time.perf_counter() - t0, me, ok
+
+
+def cpu_baseline(seed, run_s=7.0):
+    """The FP64 oracle (colour-ordered mode) on the host cores, on bounded samples.
+
+    gg -> ttbar gg: one warm-up pass that also sizes the sample, then the median of three
+    timed passes with all threads of the host share, and one pass with a single thread on
+    a sample sized the same way; gg -> ttbar and gg -> ttbar g: one pass each with all
+    threads.  Every pass covers uniforms -> Vegas map -> phase space -> cuts -> |M|^2 ->
+    Vegas accumulation.  Returns the record and the first timed sample's (x, |M|^2, pass)
+    for the direct comparison of the GPU kernels with the oracle."""
+    from oracle import philox, processes, vegas as ovegas
+    par = processes.DEFAULT_PARAMS
+    threads = _host_threads()
+    torch.set_num_threads(threads)
+    d = processes.dims(PROC)
+    edges = ovegas.uniform_grid(d, NB)
+    n0 = 256
+    dt0, _, _ = _oracle_pass(PROC, par, philox.uniforms(seed, n0, d), edges)     # warm-up
+    n = int(max(n0, min(20000, n0 * run_s / max(dt0, 1e-3))))
+    x = philox.uniforms(seed, n, d)
+    times, keep = [], None
+    for _ in range(3):
+        dt, me, ok = _oracle_pass(PROC, par, x, edges)
+        times.append(dt)
+        keep = keep or (x, me, ok)
+    t_med = float(np.median(times))
+    torch.set_num_threads(1)
+    dt1, _, _ = _oracle_pass(PROC, par, philox.uniforms(seed, n0, d), edges)
+    n1 = int(max(n0, min(20000, n0 * run_s / max(dt1, 1e-3))))
+    dt1, _, _ = _oracle_pass(PROC, par, philox.uniforms(seed + 1, n1, d), edges)
+    torch.set_num_threads(threads)
+    others = {}
+    for proc, m in (('gg_tt', 100_000), ('gg_ttg', 20_000)):
+        dp = processes.dims(proc)
+        t, _, _ = _oracle_pass(proc, par, philox.uniforms(seed, m, dp), ovegas.uniform_grid(dp, NB))
+        others[proc] = {'events': m, 'events_per_s': m / t, 'threads': threads}
+    rec = dict(value=n / t_med, unit='events/s', cores=threads, kind='oracle',
+               sample=f'{n} gg->ttbar gg events (uniforms, Vegas map, phase space, cuts, colour-ordered FP64 '
+                      f'|M|^2, Vegas accumulation), median of 3 passes after a warm-up: '
+                      f'{", ".join(f"{t:.2f}" for t in times)} s',
+               cpu_model=_cpu_model(),
+               one_thread={'events': n1, 'events_per_s': n1 / dt1, 'seconds': dt1},
+               other_processes=others)
+    return rec, keep
+
+
+def oracle_check(mf, h, prm, sample):
+    """Direct comparison of the GPU kernels with the oracle on the cpu_baseline sample:
+    the same uniforms through the GPU phase space (identity Vegas map) and matrix element
+    in both precisions, relative differences over the events that pass the cuts."""
+    x, me_o, ok = sample
+    pid = mf.PROCESS[PROC]
+    dev = torch.device('cuda', 0)
+    xt = torch.tensor(x, dtype=torch.float64, device=dev).contiguous()
+    n = x.shape[1]
+    ev = mf.mf_phase_space(h, pid, prm, n, x=xt)
+    out = {'events': int(ok.sum())}
+    for name, prec in (('fp32_mfma_bf16', mf.MF_FP32_MFMA_BF16), ('fp64', mf.MF_FP64)):
+        m = mf.matrix_element(h, pid, ev['p'], prec, prm).double().cpu().numpy()
+        rel = np.abs(m[ok] / me_o[ok] - 1.0)
+        out[name] = {'median': float(np.median(rel)), 'max': float(rel.max())}
+    return out
+
+
+def accuracy_failures(rel_fp32_fp64, vs_oracle):
+    """Reasons the run may not publish a throughput: the FP32 results off their bars (median
+    1e-5, max 1e-3 relative, no NaN) against FP64 on the last batch or against the oracle,
+    or FP64 off 1e-12 against the oracle."""
+    bad = []
+    r = rel_fp32_fp64
+    if not (r['median'] <= 1e-5 and r['max'] <= 1e-3):
+        bad.append(f'FP32 vs FP64 on the last batch: median {r["median"]}, max {r["max"]} '
+                   f'(bars 1e-5, 1e-3; NaN fails)')
+    if vs_oracle is not None:
+        a, b = vs_oracle['fp32_mfma_bf16'], vs_oracle['fp64']
+        if not (a['median'] <= 1e-5 and a['max'] <= 1e-3):
+            bad.append(f'FP32 vs oracle: median {a["median"]}, max {a["max"]}')
+        if not b['max'] <= 1e-12:
+            bad.append(f'FP64 vs oracle: max {b["max"]} (bar 1e-12)')
+    return bad
 
 
 def main():
@@ -343,8 +434,11 @@ def main():
     # relative difference FP32 vs FP64 on the last batch (same events), events passing cuts
     ok = head['pas'].bool()
     rel = ((head['me'].double() - ref['me']) / ref['me']).abs()[ok]
-    q = torch.quantile(rel[:100000].float(), torch.tensor([0.5, 0.99], device=rel.device)).tolist()
-    rel_stats = dict(median=q[0], p99=q[1], max=float(rel.max()), events=int(ok.sum()))
+    # NaN sorts last: a NaN anywhere makes the max NaN and fails the gate below
+    rel_np = rel.cpu().numpy()
+    nan = int(np.isnan(rel_np).sum())
+    rel_stats = dict(median=float(np.median(rel_np)), p99=float(np.quantile(rel_np, 0.99)),
+                     max=float('nan') if nan else float(rel_np.max()), events=int(ok.sum()), nan=nan)
     pname = [k for k, v in mf.PRECISION.items() if v == prec][0]
     fl = flops_per_event(PROC, pname)
     fl64 = flops_per_event(PROC, 'fp64')
@@ -382,8 +476,16 @@ def main():
     }
     if not args.no_extras:
         out['extras'] = extras(mf, h, prm, args.seed)
+    vs_oracle = None
     if not args.no_cpu_baseline:
-        out['cpu_baseline'] = cpu_baseline(args.seed)
+        out['cpu_baseline'], sample = cpu_baseline(args.seed)
+        vs_oracle = oracle_check(mf, h, prm, sample)
+        out['rel_err_vs_oracle'] = vs_oracle
+    bad = accuracy_failures(rel_stats, vs_oracle)
+    if bad:
+        print('bench.py: results off their accuracy bars, no throughput published:\n  ' + '\n  '.join(bad),
+              file=sys.stderr)
+        sys.exit(3)
     print(json.dumps(out))
 
 

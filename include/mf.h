@@ -99,9 +99,17 @@ typedef struct {
 
 typedef struct mf_handle_s* mf_handle;
 
-/* Create a handle bound to HIP device `device`; it owns workspace (reduction
- * partials, counters).  One handle per thread; calls on one handle from
- * several host threads must be serialised by the caller. */
+/* Create a handle bound to HIP device `device`; it owns workspace (Vegas
+ * reduction partials, about 4.2 MB, the largest any call needs; the Newton
+ * failure counter; the tile counter of persistent launches), all allocated
+ * here, so no other call allocates, frees or synchronises the device.
+ * One handle per thread; calls on one handle from several host threads must
+ * be serialised by the caller.  The workspace is shared by the handle's calls:
+ * mf_vegas_refine calls, and mf_matrix_element calls with several requests,
+ * must not run concurrently on different streams with the same handle (order
+ * them with events or use one handle per stream); on one stream they are
+ * ordered by the stream.  Errors: MF_ERR_INVALID_ARG for a bad device or NULL
+ * out, MF_ERR_NO_MEMORY if the workspace cannot be allocated. */
 mf_status mf_create(int device, mf_handle* out);
 mf_status mf_destroy(mf_handle h);
 
@@ -192,7 +200,8 @@ mf_status mf_matrix_element_vjp(mf_handle h, const mf_request* reqs, int n_reqs,
                                 const mf_params* prm, const double* edges, int nb, void* stream);
 
 /*
- * mf_vegas_refine -- the Vegas step (sect. 1): forms F = flux * w * jac * me * pass with
+ * mf_vegas_refine -- the Vegas step (sect. 1): forms F = flux * w * jac * me (events
+ * that pass the cuts and have w > 0; 0 otherwise) with
  * flux = (hbar c)^2 / (2 s) in pb GeV^2 / GeV^2 (so F is in pb), reduces
  * acc[0] = sum F, acc[1] = sum F^2, acc[2 + k*nb + i] = sum of F^2 over events
  * in bin i of dimension k (deterministic order).  flags:
@@ -204,7 +213,10 @@ mf_status mf_matrix_element_vjp(mf_handle h, const mf_request* reqs, int n_reqs,
  *   w, me      [n] required (me is f32 when me_f32 != 0); jac, pass optional;
  *   bin_idx    [d][n] required; F [n] optional output; acc [2 + d*nb] out.
  * Errors: MF_ERR_INVALID_ARG for d < 1 or d > 8, nb < 2 or nb > 64, n < 0,
- * or a NULL required pointer; MF_ERR_NO_MEMORY if workspace cannot grow.
+ * or a NULL required pointer.  It uses the handle's workspace (allocated by
+ * mf_create) and allocates nothing.  F = 0 exactly for an event that fails the
+ * cuts or has w <= 0 (a failed phase-space solve, NaN uniforms), whatever its
+ * |M|^2; a dimension whose histogram holds a non-finite value keeps its grid.
  */
 enum { MF_VEGAS_REFINE = 1, MF_VEGAS_ACCUMULATE = 2 };
 

@@ -241,6 +241,8 @@ has_precision = mf_precision_available
 
 def mf_vegas_refine(h, prm, n, d, nb, alpha, w, jac, me, pass_, bin_idx, acc, edges, F=None,
                     update_edges=True, accumulate=False, rng_counter=None, stream=None):
+    if me.dtype not in (torch.float32, torch.float64):
+        raise ValueError(f'me: dtype {me.dtype}, need torch.float32 or torch.float64')
     me_f32 = 1 if me.dtype == torch.float32 else 0
     _need(w, n, 'w', torch.float64)
     _need(jac, n, 'jac', torch.float64)

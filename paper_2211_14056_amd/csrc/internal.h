@@ -125,6 +125,11 @@ struct VegasArgs {
 };
 
 int vegas_blocks(int64_t n);
+// largest workspace of one Vegas call: at most VEGAS_MAX_BLOCKS blocks, each writing
+// 2 + d * nb <= 2 + 8 * 64 partial sums
+constexpr int VEGAS_MAX_BLOCKS = 1024;
+constexpr int VEGAS_MAX_CELLS = 2 + 8 * 64;
+constexpr size_t VEGAS_PARTIALS_MAX = (size_t)VEGAS_MAX_BLOCKS * VEGAS_MAX_CELLS;
 hipError_t launch_vegas(const VegasArgs& a, hipStream_t s);
 
 }  // namespace mf

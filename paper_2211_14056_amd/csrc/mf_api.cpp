@@ -40,8 +40,7 @@ constexpr int64_t kMaxEvents = int64_t(1) << 36;
 struct mf_handle_s {
     int device = 0;
     int n_cu = 256;
-    double* partials = nullptr;
-    size_t partials_cap = 0;           // doubles
+    double* partials = nullptr;        // Vegas block partials, the largest size any call needs
     unsigned long long* fail_dev = nullptr;
     unsigned* tile_counter = nullptr;  // persistent-batch work queue
     // launch configuration (set by mf_set_launch / the autotuner)
@@ -64,27 +63,6 @@ struct DeviceGuard {
         if (prev >= 0) hipSetDevice(prev);
     }
 };
-
-mf_status ensure_partials(mf_handle h, size_t need)
-{
-    if (h->partials_cap >= need) return MF_OK;
-    if (h->partials) {
-        // launches already enqueued may still read the old workspace; an error they
-        // left is reported here rather than dropped
-        hipError_t e = hipDeviceSynchronize();
-        if (e != hipSuccess) return hip_fail(e, "mf_vegas_refine: hipDeviceSynchronize");
-        hipFree(h->partials);
-        h->partials = nullptr;
-        h->partials_cap = 0;
-    }
-    if (hipMalloc(&h->partials, need * sizeof(double)) != hipSuccess) {
-        h->partials = nullptr;
-        return fail(MF_ERR_NO_MEMORY, "mf_vegas_refine: cannot allocate %zu bytes of workspace",
-                    need * sizeof(double));
-    }
-    h->partials_cap = need;
-    return MF_OK;
-}
 
 }  // namespace
 
@@ -117,17 +95,22 @@ mf_status mf_create(int device, mf_handle* out)
         if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
             h->n_cu = prop.multiProcessorCount;
     }
+    // all workspace is allocated here, once, at the largest size any call needs, so that
+    // no later call allocates, frees or synchronises (a captured graph keeps its pointers)
     e = hipMalloc(&h->fail_dev, sizeof(unsigned long long));
     if (e == hipSuccess) e = hipMalloc(&h->tile_counter, sizeof(unsigned));
+    if (e == hipSuccess) e = hipMalloc(&h->partials, mf::VEGAS_PARTIALS_MAX * sizeof(double));
     if (e != hipSuccess) {
         if (h->fail_dev) hipFree(h->fail_dev);
+        if (h->tile_counter) hipFree(h->tile_counter);
         delete h;
-        return fail(MF_ERR_NO_MEMORY, "mf_create: cannot allocate counters");
+        return fail(MF_ERR_NO_MEMORY, "mf_create: cannot allocate workspace");
     }
     e = hipMemset(h->fail_dev, 0, sizeof(unsigned long long));
     if (e != hipSuccess) {
         hipFree(h->fail_dev);
         hipFree(h->tile_counter);
+        hipFree(h->partials);
         delete h;
         return hip_fail(e, "mf_create: hipMemset");
     }
@@ -385,9 +368,7 @@ mf_status mf_vegas_refine(mf_handle h, const mf_params* prm, int64_t n, int d, i
     a.bin_idx = bin_idx;
     a.F = F;
     a.nblk = mf::vegas_blocks(n);
-    mf_status st = ensure_partials(h, (size_t)a.nblk * (2 + d * nb));
-    if (st != MF_OK) return st;
-    a.partials = h->partials;
+    a.partials = h->partials;          // VEGAS_PARTIALS_MAX doubles, enough for any n, d, nb
     a.acc = acc;
     a.edges = edges;
     a.update_edges = (flags & MF_VEGAS_REFINE) ? 1 : 0;

@@ -14,9 +14,10 @@
 //  * block partials (sum F, sum F^2, histogram) go to a cell-major workspace,
 //    and one workgroup sums them (a wave per cell, fixed lane order and a
 //    fixed butterfly) and then refines the grid.
-// F = flux * w * J_vegas * ME * pass is formed here from the phase-space
-// weight, the Vegas Jacobian and the matrix element, so it never round-trips
-// through memory unless the caller asks for it.
+// F = flux * w * J_vegas * ME for events that pass the cuts and have w > 0
+// (0 otherwise) is formed here from the phase-space weight, the Vegas Jacobian
+// and the matrix element, so it never round-trips through memory unless the
+// caller asks for it.
 #include "internal.h"
 
 namespace mf {
@@ -26,6 +27,7 @@ constexpr int VB = 256;           // threads per block
 constexpr int WAVES = VB / 64;
 constexpr int MAXD = 8;
 constexpr int MAXNB = 64;
+static_assert(2 + MAXD * MAXNB == VEGAS_MAX_CELLS, "workspace size");
 
 __global__ __launch_bounds__(VB) void k_vegas_accumulate(VegasArgs a)
 {
@@ -44,9 +46,12 @@ __global__ __launch_bounds__(VB) void k_vegas_accumulate(VegasArgs a)
         if (e < n) {
             const double me = a.me_f32 ? (double)static_cast<const float*>(a.me)[e]
                                        : static_cast<const double*>(a.me)[e];
-            const double ps = a.pass ? (double)a.pass[e] : 1.0;
+            const bool ps = a.pass ? a.pass[e] != 0 : true;
             const double jac = a.jac ? a.jac[e] : 1.0;
-            F = a.flux * a.w[e] * jac * me * ps;
+            const double w = a.w[e];
+            // an event outside the cuts or without weight (a failed phase-space
+            // solve, NaN uniforms) contributes exactly 0, whatever its |M|^2 holds
+            F = (ps && w > 0.0) ? a.flux * w * jac * me : 0.0;
             if (a.F) a.F[e] = F;
         }
         sf += F;
@@ -89,9 +94,14 @@ __global__ __launch_bounds__(VB) void k_vegas_accumulate(VegasArgs a)
 
 __device__ void refine_dim(const double* h, double* edges, int nb, double alpha)
 {
-    bool any = false;
-    for (int i = 0; i < nb; ++i) any = any || (h[i] > 0.0);
-    if (!any) return;
+    // a histogram without weight, or with a non-finite entry (an infinite or NaN
+    // integrand value), leaves the grid of this dimension as it is
+    bool any = false, finite = true;
+    for (int i = 0; i < nb; ++i) {
+        any = any || (h[i] > 0.0);
+        finite = finite && isfinite(h[i]);
+    }
+    if (!any || !finite) return;
     double hb[MAXNB], r[MAXNB], old[MAXNB + 1];
     hb[0] = (h[0] + h[1]) / 2.0;
     hb[nb - 1] = (h[nb - 2] + h[nb - 1]) / 2.0;
@@ -158,7 +168,7 @@ __global__ __launch_bounds__(64) void k_vegas_update(VegasArgs a)
 int vegas_blocks(int64_t n)
 {
     int64_t b = (n + VB - 1) / VB;
-    if (b > 1024) b = 1024;
+    if (b > VEGAS_MAX_BLOCKS) b = VEGAS_MAX_BLOCKS;
     if (b < 1) b = 1;
     return (int)b;
 }

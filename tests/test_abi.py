@@ -65,3 +65,16 @@ def test_process_compiler_flop_counts_are_stable():
     p = pc.GGTTProcess('gg_tt', 4)
     _, fl = pc.emit_qcd(p)
     assert fl['helicities'] == 16 and fl['per_event'] > 0
+
+
+def test_vegas_binding_rejects_a_matrix_element_of_another_dtype():
+    """The binding accepts only float32 or float64 |M|^2: a half-precision buffer would be
+    read as 8 bytes per event by the kernel.  The check runs before any device call."""
+    import torch
+    import paper_2211_14056_amd as mf
+    n, d, nb = 8, 2, 50
+    me = torch.zeros(n, dtype=torch.float16)
+    with pytest.raises(ValueError, match='me: dtype'):
+        mf.mf_vegas_refine(None, mf.params(), n, d, nb, 1.5, torch.zeros(n, dtype=torch.float64), None, me, None,
+                           torch.zeros(d, n, dtype=torch.int16), torch.zeros(2 + d * nb, dtype=torch.float64),
+                           torch.zeros(d, nb + 1, dtype=torch.float64))

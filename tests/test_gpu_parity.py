@@ -538,6 +538,82 @@ def test_vegas_deterministic(h):
     assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
 
 
+def test_vegas_bad_uniform_batch_keeps_state_finite(h):
+    """A batch holding a NaN, a negative and a >= 1 uniform goes through phase space, matrix
+    element and mf_vegas_refine: the NaN event (w = 0, NaN momenta and |M|^2) adds exactly 0,
+    the sums and the refined grid stay finite, and they equal the oracle's accumulation of
+    the same events with that event's F set to 0."""
+    proc, n, nb = 'gg_ttg', 130, 50
+    pid, d = mf.PROCESS[proc], processes.dims(proc)
+    x = philox.uniforms(50, n, d)
+    xb, bad = _bad_uniforms(x, nb)
+    dev = torch.device('cuda', 0)
+    hh = mf.Handle(0)
+    try:
+        for prec in (mf.MF_FP64, mf.MF_FP32_MFMA_BF16):
+            say('vegas refine with a NaN event', proc, n, prec)
+            ed = torch.tensor(ovegas.uniform_grid(d, nb), dtype=torch.float64, device=dev).contiguous()
+            xt = torch.tensor(xb, dtype=torch.float64, device=dev).contiguous()
+            o = mf.mf_phase_space(hh, pid, prm_of(proc), n, x=xt, edges=ed, nb=nb,
+                                  pass_=torch.empty(n, dtype=torch.uint8, device=dev),
+                                  bin_idx=torch.empty(d, n, dtype=torch.int16, device=dev),
+                                  jac=torch.empty(n, dtype=torch.float64, device=dev))
+            me = mf.matrix_element(hh, pid, o['p'], prec, prm_of(proc))
+            acc = torch.empty(2 + d * nb, dtype=torch.float64, device=dev)
+            F = torch.empty(n, dtype=torch.float64, device=dev)
+            mf.mf_vegas_refine(hh, prm_of(proc), n, d, nb, 1.5, o['w'], o['jac'], me, o['pass_'], o['bin_idx'],
+                               acc, ed, F=F)
+            torch.cuda.synchronize()
+            m = me.double().cpu().numpy()
+            w = o['w'].cpu().numpy()
+            assert np.isnan(m[5]) and w[5] == 0.0
+            a, e, f = acc.cpu().numpy(), ed.cpu().numpy(), F.cpu().numpy()
+            assert np.isfinite(a).all() and np.isfinite(e).all() and np.isfinite(f).all()
+            assert f[5] == 0.0
+            assert (np.diff(e, axis=1) >= 0).all() and (e[:, 0] == 0).all() and (e[:, -1] == 1).all()
+            ok = o['pass_'].cpu().numpy().astype(bool) & (w > 0)
+            s_ = P['sqrt_s'] ** 2
+            F_ref = np.where(ok, closed_forms.GEV2_TO_PB * w * np.where(ok, m, 0.0) / (2 * s_)
+                             * o['jac'].cpu().numpy(), 0.0)
+            sf, sf2, hist = ovegas.accumulate(F_ref, o['bin_idx'].cpu().numpy().astype(np.int64), nb)
+            assert abs(a[0] / sf - 1) < 1e-12 and abs(a[1] / sf2 - 1) < 1e-12
+            assert np.abs(a[2:].reshape(d, nb) - hist).max() <= 1e-12 * hist.max()
+            new_ref = ovegas.refine(ovegas.uniform_grid(d, nb), hist, 1.5)
+            assert np.abs(e - new_ref).max() < 1e-12
+    finally:
+        hh.close()
+
+
+def test_graph_replay_after_a_larger_call_on_the_same_handle(h):
+    """The handle's workspace is allocated once: a graph captured from a small integrator
+    still replays correctly after a second integrator with a larger batch has used the
+    same handle (the workspace is not regrown, so the graph's pointers stay valid)."""
+    from paper_2211_14056_amd.integrator import VegasIntegrator
+    hh = mf.Handle(0)
+    try:
+        say('graph replay after a larger call')
+        small = VegasIntegrator('gg_tt', precision=mf.MF_FP64, n=3000, batches=1, seed=3, handle=hh)
+        eager = []
+        for _ in range(3):
+            small.enqueue_iteration()
+            eager.append((small.acc.clone(), small.edges.clone()))
+        small.reset()
+        small.iterate(1)
+        small.capture()
+        big = VegasIntegrator('gg_ttg', precision=mf.MF_FP64, n=600_000, batches=1, seed=4, handle=hh)
+        big.iterate(1)
+        torch.cuda.synchronize()
+        got = [eager[0]]
+        for _ in range(2):
+            small.graph.replay()
+            torch.cuda.synchronize()
+            got.append((small.acc.clone(), small.edges.clone()))
+        for (a1, e1), (a2, e2) in zip(eager, got):
+            assert torch.equal(a1, a2) and torch.equal(e1, e2)
+    finally:
+        hh.close()
+
+
 def _gpu_vegas(h, proc, n, iters, seed, precision=mf.MF_FP64):
     pid = mf.PROCESS[proc]
     d = processes.dims(proc)
