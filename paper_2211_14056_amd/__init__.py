@@ -70,8 +70,10 @@ def lib():
                                         VP, I32, VP]
     L.mf_vegas_refine.argtypes = [VP, ctypes.POINTER(mf_params), I64, I32, I32, DBL, VP, VP, VP, I32, VP, VP,
                                   VP, VP, VP, I32, VP, VP]
+    L.mf_vegas_refine_noalloc.argtypes = [ctypes.POINTER(mf_params), I64, I32, I32, DBL, VP, VP, VP, I32, VP,
+                                          VP, VP, VP, VP, I32, VP, VP]
     for f in ('mf_create', 'mf_destroy', 'mf_failures', 'mf_phase_space', 'mf_matrix_element',
-              'mf_matrix_element_vjp', 'mf_vegas_refine'):
+              'mf_matrix_element_vjp', 'mf_vegas_refine', 'mf_vegas_refine_noalloc'):
         getattr(L, f).restype = I32
     _lib = L
     return L
@@ -258,6 +260,29 @@ def mf_vegas_refine(h, prm, n, d, nb, alpha, w, jac, me, pass_, bin_idx, acc, ed
                                  (MF_VEGAS_REFINE if update_edges else 0)
                                  | (MF_VEGAS_ACCUMULATE if accumulate else 0),
                                  _ptr(rng_counter), _stream(stream)))
+
+
+def mf_vegas_refine_noalloc(prm, n, d, nb, alpha, w, jac, me, pass_, bin_idx, acc, edges, F=None,
+                            update_edges=True, accumulate=False, rng_counter=None, stream=None):
+    """mf_vegas_refine without a handle and without allocation (static library workspace,
+    current device)."""
+    if me.dtype not in (torch.float32, torch.float64):
+        raise ValueError(f'me: dtype {me.dtype}, need torch.float32 or torch.float64')
+    me_f32 = 1 if me.dtype == torch.float32 else 0
+    _need(w, n, 'w', torch.float64)
+    _need(jac, n, 'jac', torch.float64)
+    _need(me, n, 'me')
+    _need(pass_, n, 'pass', torch.uint8)
+    _need(bin_idx, d * n, 'bin_idx', torch.int16)
+    _need(acc, 2 + d * nb, 'acc', torch.float64)
+    _need(edges, d * (nb + 1), 'edges', torch.float64)
+    _need(F, n, 'F', torch.float64)
+    _need(rng_counter, 1, 'rng_counter', torch.int64)
+    _check(lib().mf_vegas_refine_noalloc(ctypes.byref(prm), n, d, nb, alpha, _ptr(w), _ptr(jac), _ptr(me), me_f32,
+                                         _ptr(pass_), _ptr(bin_idx), _ptr(F), _ptr(acc), _ptr(edges),
+                                         (MF_VEGAS_REFINE if update_edges else 0)
+                                         | (MF_VEGAS_ACCUMULATE if accumulate else 0),
+                                         _ptr(rng_counter), _stream(stream)))
 
 
 def matrix_element(h, proc, p, precision=MF_FP64, prm=None, stream=None):

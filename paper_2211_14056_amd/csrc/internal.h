@@ -131,5 +131,8 @@ constexpr int VEGAS_MAX_BLOCKS = 1024;
 constexpr int VEGAS_MAX_CELLS = 2 + 8 * 64;
 constexpr size_t VEGAS_PARTIALS_MAX = (size_t)VEGAS_MAX_BLOCKS * VEGAS_MAX_CELLS;
 hipError_t launch_vegas(const VegasArgs& a, hipStream_t s);
+// device address of the library's static block-partials array (VEGAS_PARTIALS_MAX
+// doubles) on the current device
+hipError_t vegas_static_partials(double** out);
 
 }  // namespace mf

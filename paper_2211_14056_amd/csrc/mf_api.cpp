@@ -338,22 +338,19 @@ mf_status mf_matrix_element_vjp(mf_handle h, const mf_request* reqs, int n_reqs,
     return MF_OK;
 }
 
-mf_status mf_vegas_refine(mf_handle h, const mf_params* prm, int64_t n, int d, int nb, double alpha,
-                          const double* w, const double* jac, const void* me, int me_f32,
-                          const uint8_t* pass, const int16_t* bin_idx, double* F, double* acc,
-                          double* edges, int flags, uint64_t* rng_counter, void* stream)
+// validation and kernel arguments shared by mf_vegas_refine and mf_vegas_refine_noalloc
+static mf_status vegas_args(const char* who, const mf_params* prm, int64_t n, int d, int nb, double alpha,
+                            const double* w, const double* jac, const void* me, int me_f32,
+                            const uint8_t* pass, const int16_t* bin_idx, double* F, double* acc,
+                            double* edges, int flags, uint64_t* rng_counter, mf::VegasArgs& a)
 {
-    g_err.clear();
-    if (!h) return fail(MF_ERR_INVALID_ARG, "mf_vegas_refine: NULL handle");
-    if (!prm) return fail(MF_ERR_INVALID_ARG, "mf_vegas_refine: NULL params");
-    if (d < 1 || d > 8) return fail(MF_ERR_INVALID_ARG, "mf_vegas_refine: d = %d outside [1, 8]", d);
-    if (nb < 2 || nb > 64) return fail(MF_ERR_INVALID_ARG, "mf_vegas_refine: nb = %d outside [2, 64]", nb);
-    if (n < 0 || n > kMaxEvents) return fail(MF_ERR_INVALID_ARG, "mf_vegas_refine: n outside [0, 2^36]");
-    if (!acc || !edges) return fail(MF_ERR_INVALID_ARG, "mf_vegas_refine: NULL acc or edges");
-    if (n > 0 && (!w || !me || !bin_idx))
-        return fail(MF_ERR_INVALID_ARG, "mf_vegas_refine: NULL w, me or bin_idx");
-    DeviceGuard g(h->device);
-    mf::VegasArgs a{};
+    if (!prm) return fail(MF_ERR_INVALID_ARG, "%s: NULL params", who);
+    if (d < 1 || d > 8) return fail(MF_ERR_INVALID_ARG, "%s: d = %d outside [1, 8]", who, d);
+    if (nb < 2 || nb > 64) return fail(MF_ERR_INVALID_ARG, "%s: nb = %d outside [2, 64]", who, nb);
+    if (n < 0 || n > kMaxEvents) return fail(MF_ERR_INVALID_ARG, "%s: n outside [0, 2^36]", who);
+    if (!acc || !edges) return fail(MF_ERR_INVALID_ARG, "%s: NULL acc or edges", who);
+    if (n > 0 && (!w || !me || !bin_idx)) return fail(MF_ERR_INVALID_ARG, "%s: NULL w, me or bin_idx", who);
+    a = mf::VegasArgs{};
     a.n = n;
     a.d = d;
     a.nb = nb;
@@ -368,14 +365,50 @@ mf_status mf_vegas_refine(mf_handle h, const mf_params* prm, int64_t n, int d, i
     a.bin_idx = bin_idx;
     a.F = F;
     a.nblk = mf::vegas_blocks(n);
-    a.partials = h->partials;          // VEGAS_PARTIALS_MAX doubles, enough for any n, d, nb
     a.acc = acc;
     a.edges = edges;
     a.update_edges = (flags & MF_VEGAS_REFINE) ? 1 : 0;
     a.accumulate = (flags & MF_VEGAS_ACCUMULATE) ? 1 : 0;
     a.rng_counter = rng_counter;
+    return MF_OK;
+}
+
+mf_status mf_vegas_refine(mf_handle h, const mf_params* prm, int64_t n, int d, int nb, double alpha,
+                          const double* w, const double* jac, const void* me, int me_f32,
+                          const uint8_t* pass, const int16_t* bin_idx, double* F, double* acc,
+                          double* edges, int flags, uint64_t* rng_counter, void* stream)
+{
+    g_err.clear();
+    if (!h) return fail(MF_ERR_INVALID_ARG, "mf_vegas_refine: NULL handle");
+    mf::VegasArgs a;
+    mf_status st = vegas_args("mf_vegas_refine", prm, n, d, nb, alpha, w, jac, me, me_f32, pass, bin_idx, F, acc,
+                              edges, flags, rng_counter, a);
+    if (st != MF_OK) return st;
+    DeviceGuard g(h->device);
+    a.partials = h->partials;          // VEGAS_PARTIALS_MAX doubles, enough for any n, d, nb
     hipError_t e = mf::launch_vegas(a, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "mf_vegas_refine launch");
+    return MF_OK;
+}
+
+mf_status mf_vegas_refine_noalloc(const mf_params* prm, int64_t n, int d, int nb, double alpha,
+                                  const double* w, const double* jac, const void* me, int me_f32,
+                                  const uint8_t* pass, const int16_t* bin_idx, double* F, double* acc,
+                                  double* edges, int flags, uint64_t* rng_counter, void* stream)
+{
+    g_err.clear();
+    mf::VegasArgs a;
+    mf_status st = vegas_args("mf_vegas_refine_noalloc", prm, n, d, nb, alpha, w, jac, me, me_f32, pass, bin_idx,
+                              F, acc, edges, flags, rng_counter, a);
+    if (st != MF_OK) return st;
+    const size_t need = (size_t)a.nblk * (size_t)(2 + d * nb);
+    if (need > mf::VEGAS_PARTIALS_MAX)
+        return fail(MF_ERR_INVALID_ARG, "mf_vegas_refine_noalloc: %zu partial sums exceed the static workspace "
+                    "of %zu", need, (size_t)mf::VEGAS_PARTIALS_MAX);
+    hipError_t e = mf::vegas_static_partials(&a.partials);
+    if (e != hipSuccess) return hip_fail(e, "mf_vegas_refine_noalloc: address of the static workspace");
+    e = mf::launch_vegas(a, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "mf_vegas_refine_noalloc launch");
     return MF_OK;
 }
 

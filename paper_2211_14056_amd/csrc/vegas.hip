@@ -18,6 +18,8 @@
 // (0 otherwise) is formed here from the phase-space weight, the Vegas Jacobian
 // and the matrix element, so it never round-trips through memory unless the
 // caller asks for it.
+#include <mutex>
+
 #include "internal.h"
 
 namespace mf {
@@ -164,6 +166,35 @@ __global__ __launch_bounds__(64) void k_vegas_update(VegasArgs a)
 }
 
 }  // namespace
+
+// Block partials of mf_vegas_refine_noalloc: a library-owned array of the largest size
+// any call needs (VEGAS_PARTIALS_MAX doubles, 4.2 MB), one copy per device, held until
+// the process ends.  Every call writes all the cells it reads, so nothing needs clearing.
+// In host code `scratch` only names the symbol; kernels get the device address found by
+// vegas_static_partials.
+static __device__ __align__(256) double scratch[VEGAS_PARTIALS_MAX];
+
+hipError_t vegas_static_partials(double** out)
+{
+    // device address of the current device's copy, looked up once per device with that
+    // device current, then kept
+    constexpr int MAX_DEVICES = 64;
+    static std::mutex mu;
+    static double* ptr[MAX_DEVICES] = {};
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        ptr[dev] = static_cast<double*>(p);
+    }
+    *out = ptr[dev];
+    return hipSuccess;
+}
 
 int vegas_blocks(int64_t n)
 {

@@ -78,3 +78,16 @@ def test_vegas_binding_rejects_a_matrix_element_of_another_dtype():
         mf.mf_vegas_refine(None, mf.params(), n, d, nb, 1.5, torch.zeros(n, dtype=torch.float64), None, me, None,
                            torch.zeros(d, n, dtype=torch.int16), torch.zeros(2 + d * nb, dtype=torch.float64),
                            torch.zeros(d, nb + 1, dtype=torch.float64))
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason='library not built')
+def test_noalloc_vegas_validates_arguments_before_any_device_work():
+    """mf_vegas_refine_noalloc rejects bad sizes and NULL buffers on the host."""
+    import paper_2211_14056_amd as mf
+    L = mf.lib()
+    prm = mf.params()
+    for n, d, nb in ((10, 9, 50), (10, 2, 65), (10, 2, 1), (-1, 2, 50)):
+        st = L.mf_vegas_refine_noalloc(ctypes.byref(prm), n, d, nb, 1.5, None, None, None, 0, None, None, None,
+                                       None, None, 0, None, None)
+        assert st == -1, (n, d, nb)
+    assert b'mf_vegas_refine_noalloc' in L.mf_last_error()
