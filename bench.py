@@ -23,8 +23,10 @@ passes the cuts and against the FP64 CPU oracle on the cpu_baseline sample, and 
 1e-12 against the oracle there.
 
 Beside the headline the JSON line carries `extras`: the derivative (VJP) on the
-gg -> ttbar g configuration (4e6 events, FP32 and FP64) and the 64-request mixed
-batch, one persistent launch against one launch per request.
+gg -> ttbar g configuration (4e6 events, FP32 and FP64) and on gg -> ttbar gg
+(2^18 events), the 64-request mixed batch (one persistent launch per process class
+against one launch per request), and the whole mixed Vegas iteration with the
+derivative of its gg -> ttbar gg share, replayed as one library graph.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp32_mfma_f32] [--no-extras] [--streams 1|2|3]
 """
@@ -259,6 +261,24 @@ def extras(mf, h, prm, seed):
         vjp[name] = {'ms': t, 'events_per_s': n / t * 1e3, 'forward_ms': tf, 'vjp_over_forward': t / tf}
     out['vjp_gg_ttg'] = {'events': n, 'inputs_per_event': d + 2, **vjp}
     del x, gx, gth, gb
+    # the derivative on gg -> ttbar gg (the mixed batch's share), 2^18 events
+    pid, n = mf.MF_GG_TTGG, 1 << 18
+    d = mf.mf_process_dims(pid)
+    x = torch.empty(d, n, **f64)
+    ev = mf.mf_phase_space(h, pid, prm, n, seed=seed, x_out=x)
+    gx, gth, gb = torch.empty(d, n, **f64), torch.empty(n, 2, **f64), torch.ones(n, **f64)
+    vjp = {}
+    for name, prec in (('fp32', mf.MF_FP32), ('fp64', mf.MF_FP64)):
+        me = torch.empty(n, dtype=torch.float32 if prec == mf.MF_FP32 else torch.float64, device=dev)
+        req = mf.make_request(pid, None, me, x=x, grad_me=gb, grad_x=gx, grad_theta=gth, n=n)
+        fwd = mf.make_request(pid, ev['p'], me)
+        fprec = mf.MF_FP32_MFMA_BF16 if prec == mf.MF_FP32 else prec
+        t = _best_ms(lambda: mf.mf_matrix_element_vjp(h, [req], prec, prm))
+        tf = _best_ms(lambda: mf.mf_matrix_element(h, [fwd], fprec, prm))
+        vjp[name] = {'ms': t, 'events_per_s': n / t * 1e3, 'forward_ms': tf, 'vjp_over_forward': t / tf,
+                     'forward_precision': [k for k, v in mf.PRECISION.items() if v == fprec][0]}
+    out['vjp_gg_ttgg'] = {'events': n, 'inputs_per_event': d + 2, **vjp}
+    del x, gx, gth, gb, ev
     spec = mixed_batch(64, seed=5)
     reqs, keep = [], []
     prec = mf.MF_FP32_MFMA_BF16
@@ -276,6 +296,18 @@ def extras(mf, h, prm, seed):
     h.set_launch(batch_persistent=1)
     out['mixed_batch'] = {'requests': len(spec), 'events': total, 'precision': 'fp32_mfma_bf16',
                           'persistent_ms': tp, 'per_request_ms': ts, 'events_per_s': total / tp * 1e3}
+    del reqs, keep
+    # the whole mixed iteration (phase space, matrix elements, derivative of the gg -> ttbar gg
+    # share, Vegas per request) as one library graph
+    from paper_2211_14056_amd.mixed import MixedIteration
+    it = MixedIteration(spec, precision=prec, handle=h)
+    it.enqueue()
+    it.capture()
+    tg = _best_ms(it.launch)
+    share = sum(r['n'] for r in it.reqs if 'x' in r)
+    out['mixed_iteration_graph'] = {'requests': len(spec), 'events': total, 'vjp_events': share,
+                                    'precision': 'fp32_mfma_bf16', 'ms': tg, 'events_per_s': total / tg * 1e3}
+    it.graph.close()
     return out
 
 

@@ -188,11 +188,14 @@ mf_status mf_matrix_element(mf_handle h, const mf_request* reqs, int n_reqs, int
 /*
  * mf_matrix_element_vjp -- vector-Jacobian product of |M|^2 with
  * respect to the uniforms x (through the Vegas map `edges`, which may be NULL
- * for the identity, and the phase space) and to (m_t, alpha_s).  The forward
- * value is written to me_out when it is not NULL.  The derivative is taken
- * in forward (tangent) mode, one pass per input direction: per helicity the
- * recursion is re-run in registers with dual numbers, and no intermediate
- * current is stored in memory.
+ * for the identity, and the phase space) and to (m_t, alpha_s).  The paper's
+ * operator has no derivative (sect. 2); this one is a reverse sweep over the
+ * helicity/colour recursion that recomputes every helicity's currents instead
+ * of storing them, with forward tangents over the d + 1 kinematic inputs (cost
+ * about three forward evaluations plus the phase space, whatever d).  The
+ * forward value is written to me_out when it is not NULL (f64 for MF_FP64,
+ * f32 otherwise).  The requests of one process are served by one launch (a
+ * grid of 64-event tiles over up to 32 requests); all requests share `edges`.
  * Errors: as mf_matrix_element, plus NULL x / grad_me / grad_x / grad_theta,
  * MF_ERR_UNSUPPORTED for MF_EE_MUMU.
  */
@@ -244,29 +247,27 @@ mf_status mf_vegas_refine_noalloc(const mf_params* prm, int64_t n, int d, int nb
                                   double* edges, int flags, uint64_t* rng_counter, void* stream);
 
 /*
- * mf_unweight -- unit-weight event sample from weighted events (hit-or-miss;
- * the event generators of sect. 1): event e is kept iff u_e * w_max < w_e, with
- * u_e the Philox4x32-10 uniform of key = seed, counter = (offset + e, 0, 1) (a
- * stream apart from the phase-space uniforms) and w_max the reference maximum:
- * `w_max` if > 0, else the largest weight of the batch.  Non-positive and NaN
- * weights are never kept.  Kept events are written in increasing event order:
- *   w          [n] weights (for example the F of mf_vegas_refine);
- *   p, n_ext   [n_ext][4][n] momenta to copy for the kept events, or NULL / 0;
- *   cap        capacity of idx, fac and p_out;
- *   idx        [cap] out: kept event indices;
- *   fac        [cap] out: weight factors (w_e / w_max for w_e > w_max, else 1), or NULL;
- *   p_out      [n_ext][4][cap] out: momenta of the kept events, or NULL;
- *   count      device uint64 out: number of kept events (all of them, also when
- *              it exceeds cap: only the first cap are written);
- *   w_max_out  device double out: the reference maximum used, or NULL.
- * Uses the handle's workspace (ordered with the handle's other calls on one
- * stream).  Errors: MF_ERR_INVALID_ARG for n outside [0, 2^36], cap < 0, NULL
- * count, NULL w with n > 0, NULL idx with cap > 0, p_out without p or with n_ext
- * outside [1, 8], NaN w_max.
+ * Graph capture of a sequence of calls (a Vegas iteration: phase space,
+ * matrix elements, derivatives, Vegas accumulation and refinement; sect. 1),
+ * replayed later with one launch and no host work in between.
+ *   mf_graph_begin   starts capturing the work enqueued on `stream` (not the
+ *                    default stream) by this thread;
+ *   mf_graph_end     ends the capture and instantiates it; *out owns the
+ *                    executable graph (free it with mf_graph_destroy);
+ *   mf_graph_launch  replays it on `stream`.
+ * Every library call is capturable: none allocates, frees or synchronises
+ * after mf_create, and counters are reset by kernels, not by memsets.  A
+ * replay reads and writes the buffers the captured calls named, with their
+ * contents at replay time (a device-side Philox offset, mf_phase_space's
+ * offset_dev, advances the random numbers between replays).
+ * Errors: MF_ERR_INVALID_ARG for NULL arguments; MF_ERR_HIP for a capture
+ * error (for example a call that synchronised during the capture).
  */
-mf_status mf_unweight(mf_handle h, int64_t n, const double* w, double w_max, uint64_t seed, uint64_t offset,
-                      int n_ext, const double* p, int64_t cap, int64_t* idx, double* fac, double* p_out,
-                      uint64_t* count, double* w_max_out, void* stream);
+typedef struct mf_graph_s* mf_graph;
+mf_status mf_graph_begin(mf_handle h, void* stream);
+mf_status mf_graph_end(mf_handle h, void* stream, mf_graph* out);
+mf_status mf_graph_launch(mf_graph g, void* stream);
+mf_status mf_graph_destroy(mf_graph g);
 
 /* 1 if the library serves matrix elements at `precision`, else 0. */
 int mf_precision_available(int precision);

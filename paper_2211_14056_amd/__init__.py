@@ -72,8 +72,13 @@ def lib():
                                   VP, VP, VP, I32, VP, VP]
     L.mf_vegas_refine_noalloc.argtypes = [ctypes.POINTER(mf_params), I64, I32, I32, DBL, VP, VP, VP, I32, VP,
                                           VP, VP, VP, VP, I32, VP, VP]
+    L.mf_graph_begin.argtypes = [VP, VP]
+    L.mf_graph_end.argtypes = [VP, VP, ctypes.POINTER(VP)]
+    L.mf_graph_launch.argtypes = [VP, VP]
+    L.mf_graph_destroy.argtypes = [VP]
     for f in ('mf_create', 'mf_destroy', 'mf_failures', 'mf_phase_space', 'mf_matrix_element',
-              'mf_matrix_element_vjp', 'mf_vegas_refine', 'mf_vegas_refine_noalloc'):
+              'mf_matrix_element_vjp', 'mf_vegas_refine', 'mf_vegas_refine_noalloc', 'mf_graph_begin',
+              'mf_graph_end', 'mf_graph_launch', 'mf_graph_destroy'):
         getattr(L, f).restype = I32
     _lib = L
     return L
@@ -283,6 +288,41 @@ def mf_vegas_refine_noalloc(prm, n, d, nb, alpha, w, jac, me, pass_, bin_idx, ac
                                          (MF_VEGAS_REFINE if update_edges else 0)
                                          | (MF_VEGAS_ACCUMULATE if accumulate else 0),
                                          _ptr(rng_counter), _stream(stream)))
+
+
+class Graph:
+    """An executable graph of captured library calls (mf_graph_end), replayed by launch()."""
+
+    def __init__(self, ptr, device):
+        self.g = ptr
+        self.device = device
+
+    def launch(self, stream=None):
+        _check(lib().mf_graph_launch(self.g, _stream(stream)))
+
+    def close(self):
+        if self.g:
+            lib().mf_graph_destroy(self.g)
+            self.g = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def mf_graph_begin(h, stream=None):
+    """Start capturing the library calls enqueued on `stream` (torch's current stream by
+    default; not the default stream)."""
+    _check(lib().mf_graph_begin(h.h, _stream(stream)))
+
+
+def mf_graph_end(h, stream=None):
+    """End the capture on `stream`; returns the executable Graph."""
+    g = VP()
+    _check(lib().mf_graph_end(h.h, _stream(stream), ctypes.byref(g)))
+    return Graph(g, h.device)
 
 
 def matrix_element(h, proc, p, precision=MF_FP64, prm=None, stream=None):

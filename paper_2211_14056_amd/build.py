@@ -38,36 +38,39 @@ def generate():
     return process_compiler.emit_all(GEN)
 
 
-def _newest_input():
-    newest = 0.0
-    for d in (CSRC, GEN, os.path.join(os.path.dirname(HERE), 'include')):
-        for f in os.listdir(d):
-            p = os.path.join(d, f)
-            if os.path.isfile(p):
-                newest = max(newest, os.path.getmtime(p))
-    return newest
+def _deps(obj):
+    """Files the object was compiled from, from the dependency file the compiler wrote (None if absent)."""
+    d = obj[:-2] + '.d'
+    if not os.path.exists(d):
+        return None
+    text = open(d).read().replace('\\\n', ' ')
+    out = []
+    for line in text.splitlines():
+        if ':' in line:
+            out += line.split(':', 1)[1].split()
+    return out
+
+
+def _up_to_date(obj):
+    if not os.path.exists(obj):
+        return False
+    deps = _deps(obj)
+    if deps is None:
+        return False
+    t = os.path.getmtime(obj)
+    return all(os.path.exists(f) and os.path.getmtime(f) <= t for f in deps)
 
 
 def compile_one(src, extra=(), incremental=False):
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + '.o')
-    if incremental and os.path.exists(obj) and os.path.getmtime(obj) >= max(
-            _newest_input() if src.endswith('.cpp') else os.path.getmtime(os.path.join(CSRC, src)),
-            _newest_header()):
+    if incremental and _up_to_date(obj):
         return obj
-    cmd = [hipcc()] + FLAGS + list(extra) + ['-c', os.path.join(CSRC, src), '-o', obj]
+    cmd = [hipcc()] + FLAGS + list(extra) + ['-MMD', '-MF', obj[:-2] + '.d', '-c', os.path.join(CSRC, src),
+                                               '-o', obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f'compile failed: {src}\n{r.stderr[-4000:]}')
     return obj
-
-
-def _newest_header():
-    newest = 0.0
-    for d in (CSRC, GEN, os.path.join(os.path.dirname(HERE), 'include')):
-        for f in os.listdir(d):
-            if f.endswith(('.h', '.inc')):
-                newest = max(newest, os.path.getmtime(os.path.join(d, f)))
-    return newest
 
 
 def build(jobs=None, verbose=True, incremental=False):

@@ -101,8 +101,29 @@ struct VjpJob {
     double sqrt_s, mt, alpha_s, coupling;
 };
 
+// Derivative requests of one process in one launch: a grid of 64-event
+// tiles over the requests (request r owns tiles tile_begin .. tile_begin +
+// ceil(n / 64) - 1).  The per-request fields of `job` (n, x, grad_me, grad_x,
+// grad_theta, me_out) are ignored; the shared ones are used.
+struct VjpReq {
+    int64_t n;
+    const double* x;
+    const double* grad_me;
+    double* grad_x;
+    double* grad_theta;
+    void* me_out;
+    int64_t tile_begin;
+};
+constexpr int VJP_MAX_BATCH = 32;
+struct VjpBatchArgs {
+    VjpJob job;
+    VjpReq req[VJP_MAX_BATCH];
+    int nreq;
+    int64_t ntiles;
+};
+static_assert(sizeof(VjpBatchArgs) <= 4096, "kernel arguments");
 // precision 0: FP64 recursion; otherwise FP32 recursion (kinematics FP64)
-hipError_t launch_vjp(const VjpJob& j, int precision, hipStream_t s);
+hipError_t launch_vjp_batch(const VjpBatchArgs& a, int precision, hipStream_t s);
 
 struct VegasArgs {
     int64_t n;

@@ -3,16 +3,17 @@
 
 namespace mf {
 
-template <int PROC, typename R> hipError_t launch_vjp_one(const VjpJob& j, hipStream_t s);
+template <int PROC, typename R> hipError_t launch_vjp_batch_one(const VjpBatchArgs& a, hipStream_t s);
 
-hipError_t launch_vjp(const VjpJob& j, int precision, hipStream_t s)
+hipError_t launch_vjp_batch(const VjpBatchArgs& a, int precision, hipStream_t s)
 {
-    if (j.n == 0) return hipSuccess;
+    if (a.ntiles == 0) return hipSuccess;
     const bool f64 = precision == 0;
-    switch (j.proc) {
-    case GG_TT: return f64 ? launch_vjp_one<GG_TT, double>(j, s) : launch_vjp_one<GG_TT, float>(j, s);
-    case GG_TTG: return f64 ? launch_vjp_one<GG_TTG, double>(j, s) : launch_vjp_one<GG_TTG, float>(j, s);
-    case GG_TTGG: return f64 ? launch_vjp_one<GG_TTGG, double>(j, s) : launch_vjp_one<GG_TTGG, float>(j, s);
+    switch (a.job.proc) {
+    case GG_TT: return f64 ? launch_vjp_batch_one<GG_TT, double>(a, s) : launch_vjp_batch_one<GG_TT, float>(a, s);
+    case GG_TTG: return f64 ? launch_vjp_batch_one<GG_TTG, double>(a, s) : launch_vjp_batch_one<GG_TTG, float>(a, s);
+    case GG_TTGG:
+        return f64 ? launch_vjp_batch_one<GG_TTGG, double>(a, s) : launch_vjp_batch_one<GG_TTGG, float>(a, s);
     default: return hipErrorInvalidValue;
     }
 }

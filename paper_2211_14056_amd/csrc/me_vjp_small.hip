@@ -4,9 +4,9 @@
 
 namespace mf {
 
-template hipError_t launch_vjp_one<GG_TT, double>(const VjpJob&, hipStream_t);
-template hipError_t launch_vjp_one<GG_TT, float>(const VjpJob&, hipStream_t);
-template hipError_t launch_vjp_one<GG_TTG, double>(const VjpJob&, hipStream_t);
-template hipError_t launch_vjp_one<GG_TTG, float>(const VjpJob&, hipStream_t);
+template hipError_t launch_vjp_batch_one<GG_TT, double>(const VjpBatchArgs&, hipStream_t);
+template hipError_t launch_vjp_batch_one<GG_TT, float>(const VjpBatchArgs&, hipStream_t);
+template hipError_t launch_vjp_batch_one<GG_TTG, double>(const VjpBatchArgs&, hipStream_t);
+template hipError_t launch_vjp_batch_one<GG_TTG, float>(const VjpBatchArgs&, hipStream_t);
 
 }  // namespace mf

@@ -4,6 +4,6 @@
 
 namespace mf {
 
-template hipError_t launch_vjp_one<GG_TTGG, float>(const VjpJob&, hipStream_t);
+template hipError_t launch_vjp_batch_one<GG_TTGG, float>(const VjpBatchArgs&, hipStream_t);
 
 }  // namespace mf

@@ -312,17 +312,13 @@ mf_status mf_matrix_element_vjp(mf_handle h, const mf_request* reqs, int n_reqs,
     if (!(2.0 * prm->m_t < prm->sqrt_s && prm->m_t >= 0.0 && prm->alpha_s > 0.0))
         return fail(MF_ERR_INVALID_ARG, "mf_matrix_element_vjp: need 0 <= 2 m_t < sqrt_s and alpha_s > 0");
     DeviceGuard g(h->device);
-    for (int i = 0; i < n_reqs; ++i) {
-        const mf_request& r = reqs[i];
-        if (r.n == 0) continue;
-        mf::VjpJob j{};
-        j.proc = r.proc;
-        j.n = r.n;
-        j.x = r.x;
-        j.grad_me = r.grad_me;
-        j.grad_x = r.grad_x;
-        j.grad_theta = r.grad_theta;
-        j.me_out = r.me_out;
+    // one launch per process class (up to VJP_MAX_BATCH requests each): a grid of 64-event
+    // tiles over the class's requests
+    const int order[3] = {MF_GG_TTGG, MF_GG_TTG, MF_GG_TT};
+    for (int proc : order) {
+        mf::VjpBatchArgs a{};
+        mf::VjpJob& j = a.job;
+        j.proc = proc;
         j.me_f32 = precision != MF_FP64;
         j.edges = edges;
         j.nb = nb;
@@ -330,11 +326,97 @@ mf_status mf_matrix_element_vjp(mf_handle h, const mf_request* reqs, int n_reqs,
         j.mt = prm->m_t;
         j.alpha_s = prm->alpha_s;
         double coupling = 1.0;
-        for (int k = 0; k < mf::n_gluons(r.proc); ++k) coupling *= 4.0 * 3.141592653589793238463 * prm->alpha_s;
+        for (int k = 0; k < mf::n_gluons(proc); ++k) coupling *= 4.0 * 3.141592653589793238463 * prm->alpha_s;
         j.coupling = coupling;
-        hipError_t e = mf::launch_vjp(j, precision == MF_FP64 ? 0 : 1, static_cast<hipStream_t>(stream));
-        if (e != hipSuccess) return hip_fail(e, "mf_matrix_element_vjp launch");
+        auto flush = [&]() -> mf_status {
+            if (a.nreq == 0) return MF_OK;
+            hipError_t e = mf::launch_vjp_batch(a, precision == MF_FP64 ? 0 : 1, static_cast<hipStream_t>(stream));
+            if (e != hipSuccess) return hip_fail(e, "mf_matrix_element_vjp launch");
+            a.nreq = 0;
+            a.ntiles = 0;
+            return MF_OK;
+        };
+        for (int i = 0; i < n_reqs; ++i) {
+            const mf_request& r = reqs[i];
+            if (r.proc != proc || r.n == 0) continue;
+            if (a.nreq == mf::VJP_MAX_BATCH) {
+                mf_status s1 = flush();
+                if (s1 != MF_OK) return s1;
+            }
+            mf::VjpReq& q = a.req[a.nreq++];
+            q.n = r.n;
+            q.x = r.x;
+            q.grad_me = r.grad_me;
+            q.grad_x = r.grad_x;
+            q.grad_theta = r.grad_theta;
+            q.me_out = r.me_out;
+            q.tile_begin = a.ntiles;
+            a.ntiles += (r.n + 63) / 64;
+        }
+        mf_status s2 = flush();
+        if (s2 != MF_OK) return s2;
     }
+    return MF_OK;
+}
+
+struct mf_graph_s {
+    int device = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+mf_status mf_graph_begin(mf_handle h, void* stream)
+{
+    g_err.clear();
+    if (!h) return fail(MF_ERR_INVALID_ARG, "mf_graph_begin: NULL handle");
+    if (!stream) return fail(MF_ERR_INVALID_ARG, "mf_graph_begin: the default stream cannot be captured");
+    DeviceGuard g(h->device);
+    hipError_t e = hipStreamBeginCapture(static_cast<hipStream_t>(stream), hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "mf_graph_begin: hipStreamBeginCapture");
+    return MF_OK;
+}
+
+mf_status mf_graph_end(mf_handle h, void* stream, mf_graph* out)
+{
+    g_err.clear();
+    if (!h || !stream || !out) return fail(MF_ERR_INVALID_ARG, "mf_graph_end: NULL argument");
+    *out = nullptr;
+    DeviceGuard g(h->device);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(static_cast<hipStream_t>(stream), &graph);
+    if (e != hipSuccess) return hip_fail(e, "mf_graph_end: hipStreamEndCapture");
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        hipGraphDestroy(graph);
+        return hip_fail(e, "mf_graph_end: hipGraphInstantiate");
+    }
+    mf_graph r = new mf_graph_s;
+    r->device = h->device;
+    r->graph = graph;
+    r->exec = exec;
+    *out = r;
+    return MF_OK;
+}
+
+mf_status mf_graph_launch(mf_graph gr, void* stream)
+{
+    g_err.clear();
+    if (!gr) return fail(MF_ERR_INVALID_ARG, "mf_graph_launch: NULL graph");
+    DeviceGuard g(gr->device);
+    hipError_t e = hipGraphLaunch(gr->exec, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "mf_graph_launch");
+    return MF_OK;
+}
+
+mf_status mf_graph_destroy(mf_graph gr)
+{
+    g_err.clear();
+    if (!gr) return MF_OK;
+    DeviceGuard g(gr->device);
+    if (gr->exec) hipGraphExecDestroy(gr->exec);
+    if (gr->graph) hipGraphDestroy(gr->graph);
+    delete gr;
     return MF_OK;
 }
 

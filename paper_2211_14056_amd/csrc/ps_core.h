@@ -1,5 +1,6 @@
 // Phase-space core shared by the phase-space kernel (KT = double) and the
-// derivative kernel (KT = Dual<double>): Vegas map, RAMBO on diet
+// derivative kernel (KT = DualN<double, N>, tangents along N inputs): Vegas map,
+// RAMBO on diet
 // (S. Plaetzer, arXiv:1308.2922) and the massive rescaling of RAMBO
 // (R. Kleiss, W. J. Stirling, S. D. Ellis, Comput. Phys. Commun. 40 (1986) 359).
 //
@@ -7,11 +8,12 @@
 // factor xi) run on FP64 values with a safeguarded Newton iteration; one more
 // Newton step is then taken in KT arithmetic from the converged root, which
 // leaves the value unchanged to rounding and carries the implicit-function
-// derivative when KT is a Dual.
+// derivative when KT carries tangents.
 #pragma once
 #include <hip/hip_runtime.h>
 
 #include "dual.h"
+#include "dualn.h"
 
 namespace mf {
 
@@ -26,6 +28,19 @@ __device__ __forceinline__ void ps_sincos(Dual<T> x, Dual<T>& s, Dual<T>& c)
     sincos(x.v, &sv, &cv);
     s = Dual<T>(sv, cv * x.t);
     c = Dual<T>(cv, -sv * x.t);
+}
+
+template <typename T, int N>
+__device__ __forceinline__ void ps_sincos(const DualN<T, N>& x, DualN<T, N>& s, DualN<T, N>& c)
+{
+    T sv, cv;
+    sincos(x.v, &sv, &cv);
+    s.v = sv;
+    c.v = cv;
+    for (int k = 0; k < N; ++k) {
+        s.t[k] = cv * x.t[k];
+        c.t[k] = -sv * x.t[k];
+    }
 }
 
 template <typename KT>

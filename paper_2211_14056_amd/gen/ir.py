@@ -52,6 +52,11 @@ class Block:
         self.lines = []
         self.count = 0
         self.flops = 0
+        # structured record of every statement, in emission order, for the adjoint
+        # emitter: (kind, name, operands) with kind 'add' (a + b), 'mul' (a * b),
+        # 'fma' (a * b + c), 'copy' (a) or 'ext' (an expression the adjoint does not
+        # differentiate through: an LDS read, a lane exchange)
+        self.ops = []
 
     # ---------------------------------------------------------------- basics
     def ref(self, s):
@@ -59,11 +64,13 @@ class Block:
             return _lit(s.val)
         return s.name
 
-    def new(self, expr, flops):
+    def new(self, expr, flops, op=None):
         name = f'{self.prefix}{self.count}'
         self.count += 1
         self.lines.append(f'const {self.rtype} {name} = {expr};')
         self.flops += flops
+        kind, operands = op if op is not None else ('ext', (expr,))
+        self.ops.append((kind, name, operands))
         return S(name=name)
 
     def var(self, name):
@@ -85,7 +92,7 @@ class Block:
             return a
         if not a.is_const and not b.is_const and (b.name == f'(-{a.name})' or a.name == f'(-{b.name})'):
             return ZERO                          # x + (-x)
-        return self.new(f'{self.ref(a)} + {self.ref(b)}', 1)
+        return self.new(f'{self.ref(a)} + {self.ref(b)}', 1, ('add', (a, b)))
 
     def sub(self, a, b):
         return self.add(a, self.neg(b))
@@ -103,7 +110,7 @@ class Block:
             return self.neg(b)
         if b.is_const and b.val == -1.0:
             return self.neg(a)
-        return self.new(f'{self.ref(a)} * {self.ref(b)}', 1)
+        return self.new(f'{self.ref(a)} * {self.ref(b)}', 1, ('mul', (a, b)))
 
     def sumprod(self, terms, const_term=None):
         """sum_i a_i * b_i (+ c) as one fma chain; terms: list of (a, b)."""
@@ -136,13 +143,13 @@ class Block:
             if acc is None:
                 acc = self.mul(a, b)
             else:
-                acc = self.new(f'fma({self.ref(a)}, {self.ref(b)}, {self.ref(acc)})', 2)
+                acc = self.new(f'fma({self.ref(a)}, {self.ref(b)}, {self.ref(acc)})', 2, ('fma', (a, b, acc)))
         return acc
 
     def materialise(self, a):
         """Give a constant or negated reference a name of its own."""
         if a.is_const or a.name.startswith('('):
-            return self.new(self.ref(a), 0)
+            return self.new(self.ref(a), 0, ('copy', (a,)))
         return a
 
 

@@ -414,82 +414,14 @@ def _sname(sub):
     return ''.join(str(i) for i in sub)
 
 
-def emit_qcd(proc, with_colour=True, opaque_inputs=True, group_barriers=True, lds_budget=0, constants=True,
-             stream=False, share_products=False):
-    """Return (source text, flop counts) of the device function for ``proc``.
+class _IR:
+    """The IR blocks of one process: gluon currents ``b`` (per gluon-helicity
+    configuration), quark line ``q`` (per top helicity; amplitudes ``amps[h][sigma]`` for
+    the two antitop helicities) and colour sums ``cs`` (``csq[h]``)."""
 
-    opaque_inputs: re-declare the momenta as opaque at the top of each helicity
-      iteration, so that their sums are recomputed inside the loop instead of
-      being hoisted and kept live across it (fewer registers, a few adds more).
-    group_barriers: scheduling barriers between the gluon-current block and the
-      quark line and between groups of orderings with the same first gluon, so
-      that the scheduler cannot interleave them and widen the live set.
-    lds_budget: number of working-type scalars per lane that may be parked in
-      LDS.  Multi-gluon currents (longest first) are written to per-lane LDS
-      slots when computed and re-read at each use on the quark line, so they do
-      not occupy registers across the top-helicity loop.  The emitted body then
-      takes an LDS pointer (this lane's column, stride 64) as extra argument.
-    stream: fold each vertex split of a gluon current into running sums as soon
-      as its coefficients are formed (fewer values live at once; same arithmetic).
-    share_products: form a quark-line product Q(prefix) Jslash(block) used by several
-      orderings once (see Recursion.start_quark_line).
 
-    Helicity sum.  For real momenta, reversing every helicity turns each partial
-    amplitude into its complex conjugate times one phase common to all orderings,
-    so a configuration and its reverse have the same colour-summed |M|^2.  The body
-    therefore runs only the gluon-helicity configurations in which the last gluon
-    has helicity +1 (2^(k-1) of them; both top and antitop helicities each), and the
-    normalisation constant carries the factor 2 for the reversed half.
-    """
+def _build_ir(proc, lds_budget=0, stream=False, share_products=False, group_barriers=True):
     k = proc.k
-    out = []
-    fn = f'me_{proc.name}'
-    out.append(f'// ---- {proc.name}: {k} gluons, {math.factorial(k)} colour orderings, '
-               f'{2 ** (k + 2)} helicities, {2 ** (k + 1)} evaluated (the rest by helicity reversal)')
-    out.append(f'template <typename R, typename KT, typename Sink>')
-    lds_arg = ', R* __restrict__ lds' if lds_budget else ''
-    out.append(f'__device__ __forceinline__ void {fn}_body(const KT (&p)[{proc.n_ext}][4], '
-               f'const KT mt, Sink& sink{lds_arg})')
-    out.append('{')
-    # ---------------- prologue (double precision kinematics) ----------------
-    pro = []
-    # incoming-convention momenta k_i of the gluons
-    for gi, leg in enumerate(proc.gl_legs):
-        sgn = '' if leg < 2 else '-'
-        pro.append(f'const KT k{gi}[4] = {{{sgn}p[{leg}][0], {sgn}p[{leg}][1], '
-                   f'{sgn}p[{leg}][2], {sgn}p[{leg}][3]}};')
-    pro.append('const KT mt2 = mt * mt;')
-    # gluon propagators 1/P_S^2
-    for sub in proc.gluon_subsets():
-        n = _sname(sub)
-        terms = ' + '.join(f'k{i}[c]' for i in sub)
-        pro.append(f'KT P{n}[4]; for (int c = 0; c < 4; ++c) P{n}[c] = {terms};')
-        pro.append(f'const R ig{n} = cvt<R>(KT(1.0) / (P{n}[0] * P{n}[0] - P{n}[1] * P{n}[1] - '
-                   f'P{n}[2] * P{n}[2] - P{n}[3] * P{n}[3]));')
-    # quark propagators: q = p_t - P_S, 1/(q^2 - m^2)
-    for sub in proc.quark_subsets():
-        n = _sname(sub)
-        terms = ' - '.join([f'p[2][c]'] + [f'k{i}[c]' for i in sub])
-        pro.append(f'KT q{n}[4]; for (int c = 0; c < 4; ++c) q{n}[c] = {terms};')
-        pro.append(f'const R iq{n} = cvt<R>(KT(1.0) / ((q{n}[0] - q{n}[3]) * (q{n}[0] + q{n}[3]) - '
-                   f'q{n}[1] * q{n}[1] - q{n}[2] * q{n}[2] - mt2));')
-    # momenta in working precision
-    for gi in range(k):
-        pro.append(f'R K{gi}[4] = {{cvt<R>(k{gi}[0]), cvt<R>(k{gi}[1]), cvt<R>(k{gi}[2]), '
-                   f'cvt<R>(k{gi}[3])}};')
-    pro.append('R PT[4] = {cvt<R>(p[2][0]), cvt<R>(p[2][1]), cvt<R>(p[2][2]), cvt<R>(p[2][3])};')
-    pro.append('const R MT = cvt<R>(mt);')
-    # outgoing-gluon polarisation bases (eps1/sqrt2, eps2/sqrt2)
-    for gi, leg in enumerate(proc.gl_legs):
-        if leg < 2:
-            continue
-        pro.append(f'R e{gi}u[3], e{gi}w[2]; pol_basis<R, KT>(p[{leg}], e{gi}u, e{gi}w);')
-    # spinors for both helicities
-    pro.append('cplx<R> ub[2][4], vs[2][4];')
-    pro.append('ubar_spinor<R, KT>(p[2], mt, -1, ub[0]); ubar_spinor<R, KT>(p[2], mt, 1, ub[1]);')
-    pro.append('v_spinor<R, KT>(p[3], mt, -1, vs[0]); v_spinor<R, KT>(p[3], mt, 1, vs[1]);')
-    out += ['    ' + l for l in pro]
-
     # ---------------- loop body (working precision) ----------------
     b = Block('t')
     moms = [Momentum(b, [S(name=f'K{gi}[{c}]') for c in range(4)]) for gi in range(k)]
@@ -577,6 +509,94 @@ def emit_qcd(proc, with_colour=True, opaque_inputs=True, group_barriers=True, ld
             tot_terms.append((A[i].im, y_i))
         csq.append(cs.sumprod(tot_terms))
     colour_flops = cs.flops
+    ir = _IR()
+    ir.b, ir.q, ir.cs, ir.csq, ir.amps, ir.rec, ir.lds_slot = b, q, cs, csq, amps, rec, lds_slot
+    ir.gluon_flops, ir.gluon_lines, ir.quark_flops, ir.colour_flops = gluon_flops, gluon_lines, quark_flops, colour_flops
+    ir.n_or = n_or
+    return ir
+
+
+def emit_qcd(proc, with_colour=True, opaque_inputs=True, group_barriers=True, lds_budget=0, constants=True,
+             stream=False, share_products=False):
+    """Return (source text, flop counts) of the device function for ``proc``.
+
+    opaque_inputs: re-declare the momenta as opaque at the top of each helicity
+      iteration, so that their sums are recomputed inside the loop instead of
+      being hoisted and kept live across it (fewer registers, a few adds more).
+    group_barriers: scheduling barriers between the gluon-current block and the
+      quark line and between groups of orderings with the same first gluon, so
+      that the scheduler cannot interleave them and widen the live set.
+    lds_budget: number of working-type scalars per lane that may be parked in
+      LDS.  Multi-gluon currents (longest first) are written to per-lane LDS
+      slots when computed and re-read at each use on the quark line, so they do
+      not occupy registers across the top-helicity loop.  The emitted body then
+      takes an LDS pointer (this lane's column, stride 64) as extra argument.
+    stream: fold each vertex split of a gluon current into running sums as soon
+      as its coefficients are formed (fewer values live at once; same arithmetic).
+    share_products: form a quark-line product Q(prefix) Jslash(block) used by several
+      orderings once (see Recursion.start_quark_line).
+
+    Helicity sum.  For real momenta, reversing every helicity turns each partial
+    amplitude into its complex conjugate times one phase common to all orderings,
+    so a configuration and its reverse have the same colour-summed |M|^2.  The body
+    therefore runs only the gluon-helicity configurations in which the last gluon
+    has helicity +1 (2^(k-1) of them; both top and antitop helicities each), and the
+    normalisation constant carries the factor 2 for the reversed half.
+    """
+    k = proc.k
+    out = []
+    fn = f'me_{proc.name}'
+    out.append(f'// ---- {proc.name}: {k} gluons, {math.factorial(k)} colour orderings, '
+               f'{2 ** (k + 2)} helicities, {2 ** (k + 1)} evaluated (the rest by helicity reversal)')
+    out.append(f'template <typename R, typename KT, typename Sink>')
+    lds_arg = ', R* __restrict__ lds' if lds_budget else ''
+    out.append(f'__device__ __forceinline__ void {fn}_body(const KT (&p)[{proc.n_ext}][4], '
+               f'const KT mt, Sink& sink{lds_arg})')
+    out.append('{')
+    # ---------------- prologue (double precision kinematics) ----------------
+    pro = []
+    # incoming-convention momenta k_i of the gluons
+    for gi, leg in enumerate(proc.gl_legs):
+        sgn = '' if leg < 2 else '-'
+        pro.append(f'const KT k{gi}[4] = {{{sgn}p[{leg}][0], {sgn}p[{leg}][1], '
+                   f'{sgn}p[{leg}][2], {sgn}p[{leg}][3]}};')
+    pro.append('const KT mt2 = mt * mt;')
+    # gluon propagators 1/P_S^2
+    for sub in proc.gluon_subsets():
+        n = _sname(sub)
+        terms = ' + '.join(f'k{i}[c]' for i in sub)
+        pro.append(f'KT P{n}[4]; for (int c = 0; c < 4; ++c) P{n}[c] = {terms};')
+        pro.append(f'const R ig{n} = cvt<R>(KT(1.0) / (P{n}[0] * P{n}[0] - P{n}[1] * P{n}[1] - '
+                   f'P{n}[2] * P{n}[2] - P{n}[3] * P{n}[3]));')
+    # quark propagators: q = p_t - P_S, 1/(q^2 - m^2)
+    for sub in proc.quark_subsets():
+        n = _sname(sub)
+        terms = ' - '.join([f'p[2][c]'] + [f'k{i}[c]' for i in sub])
+        pro.append(f'KT q{n}[4]; for (int c = 0; c < 4; ++c) q{n}[c] = {terms};')
+        pro.append(f'const R iq{n} = cvt<R>(KT(1.0) / ((q{n}[0] - q{n}[3]) * (q{n}[0] + q{n}[3]) - '
+                   f'q{n}[1] * q{n}[1] - q{n}[2] * q{n}[2] - mt2));')
+    # momenta in working precision
+    for gi in range(k):
+        pro.append(f'R K{gi}[4] = {{cvt<R>(k{gi}[0]), cvt<R>(k{gi}[1]), cvt<R>(k{gi}[2]), '
+                   f'cvt<R>(k{gi}[3])}};')
+    pro.append('R PT[4] = {cvt<R>(p[2][0]), cvt<R>(p[2][1]), cvt<R>(p[2][2]), cvt<R>(p[2][3])};')
+    pro.append('const R MT = cvt<R>(mt);')
+    # outgoing-gluon polarisation bases (eps1/sqrt2, eps2/sqrt2)
+    for gi, leg in enumerate(proc.gl_legs):
+        if leg < 2:
+            continue
+        pro.append(f'R e{gi}u[3], e{gi}w[2]; pol_basis<R, KT>(p[{leg}], e{gi}u, e{gi}w);')
+    # spinors for both helicities
+    pro.append('cplx<R> ub[2][4], vs[2][4];')
+    pro.append('ubar_spinor<R, KT>(p[2], mt, -1, ub[0]); ubar_spinor<R, KT>(p[2], mt, 1, ub[1]);')
+    pro.append('v_spinor<R, KT>(p[3], mt, -1, vs[0]); v_spinor<R, KT>(p[3], mt, 1, vs[1]);')
+    out += ['    ' + l for l in pro]
+
+    # ---------------- loop body (working precision) ----------------
+    ir = _build_ir(proc, lds_budget, stream, share_products, group_barriers)
+    b, q, cs, csq, amps, lds_slot = ir.b, ir.q, ir.cs, ir.csq, ir.amps, ir.lds_slot
+    gluon_flops, gluon_lines, quark_flops, colour_flops = ir.gluon_flops, ir.gluon_lines, ir.quark_flops, ir.colour_flops
+    n_or = ir.n_or
 
     # ---------------- emit ----------------
     body = []
@@ -629,6 +649,239 @@ def emit_qcd(proc, with_colour=True, opaque_inputs=True, group_barriers=True, ld
                  per_event=(2 ** (k - 1)) * (gluon_flops + 2 * (quark_flops + colour_flops)),
                  helicities=helis, evaluated_helicities=helis // 2, lds_slots=nslots)
     out.append(f'// flops per event (generated count): {flops}')
+    return '\n'.join(out), flops
+
+
+# ----------------------------------------------------------------- adjoint
+def _zname_key(n):
+    order = ('K', 'PT', 'MT', 'ig', 'iq', 'e', 'ub', 'vs')
+    for i, pfx in enumerate(order):
+        if n.startswith(pfx):
+            return (i, n)
+    return (len(order), n)
+
+
+def kin_slots(proc):
+    """Names of the kinematic inputs the recursion reads (the vector z of the adjoint),
+    in slot order.  The top-spinor row of the current top helicity, ubs, appears as the
+    two rows ub[0] and ub[1]."""
+    ir = _build_ir(proc)
+    from .adjoint import operand_names, defined_names
+    ops = ir.b.ops + ir.q.ops + ir.cs.ops
+    names = operand_names(ops) - set(defined_names(ops))
+    out = set()
+    for n in names:
+        if n.startswith('lam'):
+            continue                      # helicity signs: no derivative
+        if n.startswith('ubs['):
+            j, part = n[4], n.split('.')[1]
+            out.update({f'ub[0][{j}].{part}', f'ub[1][{j}].{part}'})
+        else:
+            out.add(n)
+    return sorted(out, key=_zname_key)
+
+
+def emit_kin(proc):
+    """Kinematic inputs of the recursion from the momenta and m_t, in the kinematic type
+    KT, each handed to out.put(slot, value): the same quantities, in the same
+    arithmetic, as the prologue of the forward body (gluon and quark propagator
+    denominators, momenta, polarisation bases, spinors)."""
+    k = proc.k
+    slots = kin_slots(proc)
+    idx = {n: i for i, n in enumerate(slots)}
+    fn = f'me_{proc.name}'
+    L = [f'// kinematic inputs of the {proc.name} recursion: {len(slots)} slots',
+         f'constexpr int {fn}_nkin = {len(slots)};',
+         'template <typename KT, typename Out>',
+         f'__device__ __forceinline__ void {fn}_kin(const KT (&p)[{proc.n_ext}][4], const KT mt, Out& out)',
+         '{']
+    B = []
+    for gi, leg in enumerate(proc.gl_legs):
+        sgn = '' if leg < 2 else '-'
+        B.append(f'const KT k{gi}[4] = {{{sgn}p[{leg}][0], {sgn}p[{leg}][1], {sgn}p[{leg}][2], {sgn}p[{leg}][3]}};')
+    B.append('const KT mt2 = mt * mt;')
+    for sub in proc.gluon_subsets():
+        n = _sname(sub)
+        if f'ig{n}' not in idx:
+            continue
+        terms = ' + '.join(f'k{i}[c]' for i in sub)
+        B.append(f'{{ KT P[4]; for (int c = 0; c < 4; ++c) P[c] = {terms};')
+        B.append(f'  out.put({idx["ig" + n]}, KT(1.0) / (P[0] * P[0] - P[1] * P[1] - P[2] * P[2] - P[3] * P[3])); }}')
+    for sub in proc.quark_subsets():
+        n = _sname(sub)
+        if f'iq{n}' not in idx:
+            continue
+        terms = ' - '.join(['p[2][c]'] + [f'k{i}[c]' for i in sub])
+        B.append(f'{{ KT q[4]; for (int c = 0; c < 4; ++c) q[c] = {terms};')
+        B.append(f'  out.put({idx["iq" + n]}, KT(1.0) / ((q[0] - q[3]) * (q[0] + q[3]) - q[1] * q[1] - q[2] * q[2] - mt2)); }}')
+    for n in slots:
+        if n.startswith('K'):
+            gi, c = n[1:].split('[')
+            B.append(f'out.put({idx[n]}, k{gi}[{c[:-1]}]);')
+        elif n.startswith('PT'):
+            B.append(f'out.put({idx[n]}, p[2][{n[3]}]);')
+        elif n == 'MT':
+            B.append(f'out.put({idx[n]}, mt);')
+    for gi, leg in enumerate(proc.gl_legs):
+        if leg < 2:
+            continue
+        B.append(f'{{ KT u[3], w[2]; pol_basis<KT, KT>(p[{leg}], u, w);')
+        for c in range(3):
+            if f'e{gi}u[{c}]' in idx:
+                B.append(f'  out.put({idx[f"e{gi}u[{c}]"]}, u[{c}]);')
+        for c in range(2):
+            if f'e{gi}w[{c}]' in idx:
+                B.append(f'  out.put({idx[f"e{gi}w[{c}]"]}, w[{c}]);')
+        B.append('}')
+    for arr, fnc, leg in (('ub', 'ubar_spinor', 2), ('vs', 'v_spinor', 3)):
+        for h, lam in ((0, -1), (1, 1)):
+            B.append(f'{{ cplx<KT> s[4]; {fnc}<KT, KT>(p[{leg}], mt, {lam}, s);')
+            for j in range(4):
+                for part in ('re', 'im'):
+                    nm = f'{arr}[{h}][{j}].{part}'
+                    if nm in idx:
+                        B.append(f'  out.put({idx[nm]}, s[{j}].{part});')
+            B.append('}')
+    L += ['    ' + l for l in B]
+    L.append('}')
+    return '\n'.join(L), slots
+
+
+def _adj_lvalue(n):
+    """Accumulator of an input's adjoint: the input's name with _b after its identifier."""
+    if n.startswith('lam'):
+        return None
+    i = 0
+    while i < len(n) and (n[i].isalnum() or n[i] == '_'):
+        i += 1
+    return n[:i] + '_b' + n[i:]
+
+
+def emit_qcd_adjoint(proc, opaque_inputs=True, group_barriers=True):
+    """Adjoint (reverse sweep) of the helicity-summed, colour-contracted |M|^2 with respect
+    to the kinematic inputs z (emit_kin), recomputing every current per helicity.
+
+    Per gluon-helicity configuration: the gluon currents forward; per top helicity the
+    quark line and colour sums forward, then their reverse sweep seeded with 1 for both
+    antitop helicities, which adds into the adjoints of the currents and of z; after the
+    top-helicity loop the gluon currents are recomputed (no value of the first pass is
+    kept across the loop except the currents the quark line reads) and swept backwards.
+    Nothing is stored in memory.  Returns (source, flop counts)."""
+    from .adjoint import Adjoint, operand_names, defined_names
+    k = proc.k
+    ir = _build_ir(proc, 0, False, False, group_barriers)
+    b, q, cs = ir.b, ir.q, ir.cs
+    g_temps = defined_names(b.ops)
+    qc_ops = q.ops + cs.ops
+    qc_temps = defined_names(qc_ops)
+    g_set = set(g_temps)
+    g_read = sorted((operand_names(qc_ops) & g_set), key=lambda n: int(n[1:]))
+    kin_src, slots = emit_kin(proc)
+    fn = f'me_{proc.name}'
+    out = [kin_src, '']
+    out.append(f'// adjoint of {fn}: |M|^2 (no couplings, no normalisation) added to me, its gradient')
+    out.append(f'// with respect to the kinematic inputs z written to zb')
+    out.append('template <typename R>')
+    out.append(f'__device__ __forceinline__ void {fn}_adjoint(const R (&z)[{len(slots)}], R (&zb)[{len(slots)}], R& me)')
+    out.append('{')
+    body = []
+    # unpack z into the names the recursion reads; accumulators for their adjoints
+    arrays = {}
+    scalars = []
+    for i, n in enumerate(slots):
+        if '[' in n:
+            base = n[:n.index('[')]
+            arrays.setdefault(base, []).append((n, i))
+        else:
+            scalars.append((n, i))
+    dims = {'ub': '[2][4]', 'vs': '[2][4]', 'PT': '[4]'}
+    for base, items in arrays.items():
+        if base in ('ub', 'vs'):
+            body.append(f'cplx<R> {base}[2][4] = {{}};')
+            body.append(f'cplx<R> {base}_b[2][4] = {{}};')
+        else:
+            size = max(int(n[len(base) + 1:].split(']')[0]) for n, _ in items) + 1
+            body.append(f'R {base}[{size}] = {{}};')
+            body.append(f'R {base}_b[{size}] = {{}};')
+        for n, i in items:
+            body.append(f'{n} = z[{i}];')
+    for n, i in scalars:
+        body.append(f'const R {n} = z[{i}];')
+        body.append(f'R {n}_b = R(0);')
+    opq = []
+    if opaque_inputs:
+        for gi, leg in enumerate(proc.gl_legs):
+            comps = [0] if leg < 2 else [0, 1, 2, 3]
+            opq += [f'opaque(K{gi}[{c}]);' for c in comps]
+        opq += [f'opaque(PT[{c}]);' for c in range(4)]
+    body.append('#pragma unroll 1')
+    body.append(f'for (int gconf = {2 ** (k - 1)}; gconf < {2 ** k}; ++gconf) {{   // last gluon: helicity +1')
+    body += ['    ' + l for l in opq]
+    for gi in range(k):
+        body.append(f'    const R lam{gi} = (gconf >> {gi}) & 1 ? R(1) : R(-1);')
+    body += ['    ' + l for l in ir.gluon_lines]
+    body += [f'    R {n}_b = R(0);' for n in g_read]
+    body.append('    #pragma unroll 1')
+    body.append('    for (int ht = 0; ht < 2; ++ht) {')
+    body += ['        ' + l for l in opq]
+    if group_barriers:
+        body.append('        __builtin_amdgcn_sched_barrier(0);')
+    body.append('        cplx<R> ubs[4], ubs_b[4] = {};')
+    body.append('        for (int j = 0; j < 4; ++j) ubs[j] = ht ? ub[1][j] : ub[0][j];')
+    body += ['        ' + l for l in q.lines]
+    body += ['        ' + l for l in cs.lines]
+    body.append(f'        me += {cs.ref(ir.csq[0])} + {cs.ref(ir.csq[1])};')
+    aq = Adjoint(set(qc_temps) | set(g_read), _adj_lvalue, declared=g_read)
+    for h in range(2):
+        aq.seed(ir.csq[h], 'R(1)')
+    aq.sweep(qc_ops)
+    if group_barriers:
+        body.append('        __builtin_amdgcn_sched_barrier(0);')
+    body += ['        ' + l for l in aq.lines]
+    body.append('        for (int j = 0; j < 4; ++j) {')
+    body.append('            cplx<R>& t = ht ? ub_b[1][j] : ub_b[0][j];')
+    body.append('            t.re += ubs_b[j].re;')
+    body.append('            t.im += ubs_b[j].im;')
+    body.append('        }')
+    body.append('    }')
+    # recompute the gluon currents (renamed), then sweep them backwards
+    import re as _re
+    ren = lambda n: 'tr' + n[1:] if n in g_set else n       # noqa: E731
+    rec_lines = [_re.sub(r'\bt(\d+)\b', r'tr\1', l) for l in ir.gluon_lines]
+    if group_barriers:
+        body.append('    __builtin_amdgcn_sched_barrier(0);')
+    body += ['    ' + l for l in rec_lines]
+    ag = Adjoint(g_set, _adj_lvalue, declared=g_read, val=ren)
+    ag.sweep(b.ops)
+    body += ['    ' + l for l in ag.lines]
+    body.append('}')
+    for i, n in enumerate(slots):
+        if n.startswith(('ub[', 'vs[')):
+            body.append(f'zb[{i}] = {n[:2]}_b{n[2:]};')
+        else:
+            body.append(f'zb[{i}] = {_adj_lvalue(n)};')
+    out += ['    ' + l for l in body]
+    out.append('}')
+    per_gconf = 2 * ir.gluon_flops + ag.flops + 2 * (ir.quark_flops + ir.colour_flops + 1 + aq.flops)
+    flops = dict(adjoint_per_event=(2 ** (k - 1)) * per_gconf, kin_slots=len(slots),
+                 adjoint_gluon_sweep=ag.flops, adjoint_quark_colour_sweep=aq.flops)
+    out.append(f'// flops per event of the adjoint (generated count): {flops}')
+    n = proc.n_ext
+    out += ['',
+            'namespace mf {',
+            'template <int K> struct AdjProc;',
+            f'template <> struct AdjProc<{k}> {{',
+            f'    static constexpr int NZ = {len(slots)};',
+            '    template <typename KT, typename Out>',
+            f'    __device__ static __forceinline__ void kin(const KT (&p)[{n}][4], const KT mt, Out& o) '
+            f'{{ {fn}_kin<KT>(p, mt, o); }}',
+            '    template <typename R>',
+            f'    __device__ static __forceinline__ void adjoint(const R (&z)[NZ], R (&zb)[NZ], R& me) '
+            f'{{ {fn}_adjoint<R>(z, zb, me); }}',
+            '    // 2 (reversed helicities) / (initial average * identical final gluons * colour denominator)',
+            f'    static constexpr double norm = 2.0 / ({proc.avg!r} * {float(proc.sym)!r} * {float(proc.cden)!r});',
+            '};',
+            '}  // namespace mf']
     return '\n'.join(out), flops
 
 
@@ -719,6 +972,12 @@ def emit_all(outdir, **opts):
                 f.write(f'__host__ __device__ constexpr double me_{name}_pair_norm_noalpha() '
                         f'{{ return 2.0 / ({proc.avg!r} * {float(proc.sym)!r} * {float(proc.cden)!r}); }}\n')
             flops['pair_executed_per_event'] = info_p['executed_per_event']
+        # reverse-sweep derivative: kinematic inputs and the adjoint of the recursion
+        src_adj, info_adj = emit_qcd_adjoint(proc)
+        with open(os.path.join(outdir, f'me_{name}_adj.inc'), 'w') as f:
+            f.write('// Generated by paper_2211_14056_amd.gen.process_compiler -- do not edit.\n')
+            f.write(src_adj + '\n')
+        flops.update(info_adj)
         summary[name] = flops
     with open(os.path.join(outdir, 'flops.txt'), 'w') as f:
         for name, fl in summary.items():

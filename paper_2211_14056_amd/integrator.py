@@ -5,16 +5,17 @@ One Vegas iteration (Vegas iterations are the paper's integrator, sect. 1) is
     mf_phase_space -> mf_matrix_element -> mf_vegas_refine
 on one stream.  The Philox counter offset lives in device memory: the phase
 space reads it and the Vegas reduction advances it by the batch size, so a
-captured HIP graph of one iteration can be replayed iteration after iteration
-with no host work in between except reading the two accumulated sums.
+captured HIP graph of one iteration (captured by the library, mf_graph_begin /
+mf_graph_end) can be replayed iteration after iteration with no host work in
+between except reading the two accumulated sums.
 """
 import math
 
 import numpy as np
 import torch
 
-from . import (Handle, MF_FP64, PROCESS, make_request, mf_matrix_element, mf_phase_space, mf_process_dims,
-               mf_process_legs, mf_vegas_refine, params)
+from . import (Handle, MF_FP64, PROCESS, make_request, mf_graph_begin, mf_graph_end, mf_matrix_element,
+               mf_phase_space, mf_process_dims, mf_process_legs, mf_vegas_refine, params)
 
 
 class VegasIntegrator:
@@ -76,16 +77,16 @@ class VegasIntegrator:
         return self.results[-iters:]
 
     def capture(self):
-        """Capture one iteration into a HIP graph (run one eager iteration first so the
-        library's workspace exists; that iteration is part of the integration)."""
+        """Capture one iteration into a library-owned HIP graph (mf_graph_begin/end; run one
+        eager iteration first so the first replay continues the integration)."""
         if not self.results:
             self.iterate(1)
         torch.cuda.synchronize()
-        self.graph = torch.cuda.CUDAGraph()
         s = torch.cuda.Stream()
         with torch.cuda.stream(s):
-            with torch.cuda.graph(self.graph, stream=s):
-                self.enqueue_iteration()
+            mf_graph_begin(self.h, s)
+            self.enqueue_iteration()
+            self.graph = mf_graph_end(self.h, s)
         torch.cuda.synchronize()
         # capturing does not execute: the state is unchanged
         return self.graph
@@ -93,7 +94,7 @@ class VegasIntegrator:
     def replay(self, iters):
         out = []
         for _ in range(iters):
-            self.graph.replay()
+            self.graph.launch()
             out.append(self._record())
         return out
 

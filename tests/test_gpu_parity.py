@@ -540,7 +540,7 @@ def test_vegas_deterministic(h):
 
 def test_vegas_bad_uniform_batch_keeps_state_finite(h):
     """A batch holding a NaN, a negative and a >= 1 uniform goes through phase space, matrix
-    element and mf_vegas_refine: the NaN event (w = 0, NaN momenta and |M|^2) adds exactly 0,
+    element and mf_vegas_refine: the NaN event (NaN momenta, |M|^2 and weight) adds exactly 0,
     the sums and the refined grid stay finite, and they equal the oracle's accumulation of
     the same events with that event's F set to 0."""
     proc, n, nb = 'gg_ttg', 130, 50
@@ -566,7 +566,7 @@ def test_vegas_bad_uniform_batch_keeps_state_finite(h):
             torch.cuda.synchronize()
             m = me.double().cpu().numpy()
             w = o['w'].cpu().numpy()
-            assert np.isnan(m[5]) and w[5] == 0.0
+            assert np.isnan(m[5]) and not w[5] > 0.0       # NaN in, NaN out (or a failed solve: 0)
             a, e, f = acc.cpu().numpy(), ed.cpu().numpy(), F.cpu().numpy()
             assert np.isfinite(a).all() and np.isfinite(e).all() and np.isfinite(f).all()
             assert f[5] == 0.0
@@ -605,7 +605,7 @@ def test_graph_replay_after_a_larger_call_on_the_same_handle(h):
         torch.cuda.synchronize()
         got = [eager[0]]
         for _ in range(2):
-            small.graph.replay()
+            small.graph.launch()
             torch.cuda.synchronize()
             got.append((small.acc.clone(), small.edges.clone()))
         for (a1, e1), (a2, e2) in zip(eager, got):
@@ -708,7 +708,7 @@ def _normwise(a, b):
     return np.abs(a - b).max(0) / np.abs(b).max(0)
 
 
-VJP_N = {'gg_tt': 64, 'gg_ttg': 24, 'gg_ttgg': 4}
+VJP_N = {'gg_tt': 64, 'gg_ttg': 97, 'gg_ttgg': 69}     # full waves plus ragged tails
 
 
 @pytest.mark.parametrize('proc', ['gg_tt', 'gg_ttg', 'gg_ttgg'])
@@ -811,6 +811,87 @@ def test_vjp_full_size_ttg_sampled(h):
     ga = np.concatenate([gx[:, idx].cpu().numpy(), gth[idx, :1].cpu().numpy().T], 0)
     gbb = np.concatenate([gx_o, gth_o[:, :1].T], 0)
     assert _normwise(ga, gbb).max() < 1e-2
+
+
+def test_vjp_several_requests_in_one_call_equal_separate_calls(h):
+    """Requests of all three processes in one mf_matrix_element_vjp call (one launch per
+    process, a grid of 64-event tiles over its requests, ragged sizes) give bit for bit the
+    results of one call per request."""
+    specs = [('gg_ttgg', 70), ('gg_tt', 1), ('gg_ttg', 130), ('gg_ttgg', 64), ('gg_tt', 200), ('gg_ttg', 3)]
+    dev = torch.device('cuda', 0)
+    for prec in (mf.MF_FP32, mf.MF_FP64):
+        say('vjp batch vs separate', prec)
+        bufs, reqs = [], []
+        for i, (proc, n) in enumerate(specs):
+            pid, d = mf.PROCESS[proc], processes.dims(proc)
+            x = torch.tensor(philox.uniforms(60 + i, n, d), dtype=torch.float64, device=dev).contiguous()
+            b = dict(x=x, gb=torch.linspace(0.5, 1.5, n, dtype=torch.float64, device=dev),
+                     gx=torch.empty(d, n, dtype=torch.float64, device=dev),
+                     gth=torch.empty(n, 2, dtype=torch.float64, device=dev),
+                     me=torch.empty(n, dtype=torch.float64 if prec == mf.MF_FP64 else torch.float32, device=dev))
+            bufs.append(b)
+            reqs.append(mf.make_request(pid, None, b['me'], x=x, grad_me=b['gb'], grad_x=b['gx'],
+                                        grad_theta=b['gth'], n=n))
+        mf.mf_matrix_element_vjp(h, reqs, prec, prm_of('gg_tt'))
+        torch.cuda.synchronize()
+        together = [{k: v.clone() for k, v in b.items()} for b in bufs]
+        for r in reqs:
+            mf.mf_matrix_element_vjp(h, [r], prec, prm_of('gg_tt'))
+        torch.cuda.synchronize()
+        for a, b in zip(together, bufs):
+            for k in ('gx', 'gth', 'me'):
+                assert torch.equal(a[k], b[k]), k
+
+
+def test_mixed_iteration_graph_equals_eager_and_share_vjp_matches_oracle(h):
+    """The 64-request mixed iteration (phase space, one matrix-element call over all
+    requests, one derivative call over the gg -> ttbar gg share, Vegas per request) captured
+    in one library graph: three replays equal three eager iterations bit for bit (sums,
+    grids, derivatives), and the share's derivative matches the oracle's reverse mode on
+    sampled events."""
+    from oracle import grad as ograd
+    from paper_2211_14056_amd.mixed import MixedIteration
+    from paper_2211_14056_amd.workloads import mixed_batch
+    spec = mixed_batch(64, seed=5, scale=0.004)
+    say('mixed iteration', sum(n for _, n in spec), 'events')
+    eager = MixedIteration(spec, handle=h)
+    ref, grids = [], []
+    for _ in range(3):
+        grids.append(eager.edges['gg_ttgg'].clone())
+        eager.enqueue()
+        torch.cuda.synchronize()
+        ref.append(eager.state())
+    it = MixedIteration(spec, handle=h)
+    it.enqueue()
+    torch.cuda.synchronize()
+    got = [it.state()]
+    it.capture()
+    for _ in range(2):
+        it.launch()
+        torch.cuda.synchronize()
+        junk = torch.randn(1000, device='cuda').sum()       # unrelated eager work between replays
+        got.append(it.state())
+    for a, b in zip(ref, got):
+        assert a.keys() == b.keys()
+        for k in a:
+            assert torch.equal(a[k], b[k]), k
+    # derivative of the gg -> ttbar gg share (last iteration) against the oracle
+    ed = grids[2].cpu().numpy()
+    checked = 0
+    for i, r in enumerate(eager.reqs):
+        if 'x' not in r or checked >= 2:
+            continue
+        idx = np.random.default_rng(i).choice(r['n'], min(8, r['n']), replace=False)
+        x = r['x'][:, idx].cpu().numpy()
+        me_o, gx_o, gth_o = ograd.vjp('gg_ttgg', P, x, np.ones(len(idx)), edges=ed)
+        ga = np.concatenate([r['gx'][:, idx].cpu().numpy(), r['gth'][idx, :1].cpu().numpy().T], 0)
+        gbb = np.concatenate([gx_o, gth_o[:, :1].T], 0)
+        err = _normwise(ga, gbb)
+        say('  share vjp request', i, 'median', np.median(err), 'max', err.max())
+        assert np.median(err) < 1e-4 and err.max() < 1e-2
+        assert np.abs(r['gth'][idx, 1].cpu().numpy() / gth_o[:, 1] - 1).max() < 1e-3
+        checked += 1
+    assert checked == 2
 
 
 def test_autograd_function(h):
@@ -955,7 +1036,7 @@ def test_graph_replay_equals_eager(h):
     g = vi.capture()
     replayed = [(eager[0][0], eager[0][1])]
     for _ in range(3):
-        g.replay()
+        g.launch()
         torch.cuda.synchronize()
         # unrelated eager work between replays
         junk = torch.randn(1000, device='cuda').sum()
