@@ -247,6 +247,31 @@ mf_status mf_vegas_refine_noalloc(const mf_params* prm, int64_t n, int d, int nb
                                   double* edges, int flags, uint64_t* rng_counter, void* stream);
 
 /*
+ * mf_unweight -- unit-weight event sample from weighted events (hit-or-miss;
+ * the event generators of sect. 1): event e is kept iff u_e * w_max < w_e, with
+ * u_e the Philox4x32-10 uniform of key = seed, counter = (offset + e, 0, 1) (a
+ * stream apart from the phase-space uniforms) and w_max the reference maximum:
+ * `w_max` if > 0, else the largest weight of the batch.  Non-positive and NaN
+ * weights are never kept.  Kept events are written in increasing event order:
+ *   w          [n] weights (for example the F of mf_vegas_refine);
+ *   p, n_ext   [n_ext][4][n] momenta to copy for the kept events, or NULL / 0;
+ *   cap        capacity of idx, fac and p_out;
+ *   idx        [cap] out: kept event indices;
+ *   fac        [cap] out: weight factors (w_e / w_max for w_e > w_max, else 1), or NULL;
+ *   p_out      [n_ext][4][cap] out: momenta of the kept events, or NULL;
+ *   count      device uint64 out: number of kept events (all of them, also when
+ *              it exceeds cap: only the first cap are written);
+ *   w_max_out  device double out: the reference maximum used, or NULL.
+ * Uses the handle's workspace (ordered with the handle's other calls on one
+ * stream).  Errors: MF_ERR_INVALID_ARG for n outside [0, 2^36], cap < 0, NULL
+ * count, NULL w with n > 0, NULL idx with cap > 0, p_out without p or with n_ext
+ * outside [1, 8], NaN w_max.
+ */
+mf_status mf_unweight(mf_handle h, int64_t n, const double* w, double w_max, uint64_t seed, uint64_t offset,
+                      int n_ext, const double* p, int64_t cap, int64_t* idx, double* fac, double* p_out,
+                      uint64_t* count, double* w_max_out, void* stream);
+
+/*
  * Graph capture of a sequence of calls (a Vegas iteration: phase space,
  * matrix elements, derivatives, Vegas accumulation and refinement; sect. 1),
  * replayed later with one launch and no host work in between.

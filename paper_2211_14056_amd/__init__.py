@@ -72,13 +72,14 @@ def lib():
                                   VP, VP, VP, I32, VP, VP]
     L.mf_vegas_refine_noalloc.argtypes = [ctypes.POINTER(mf_params), I64, I32, I32, DBL, VP, VP, VP, I32, VP,
                                           VP, VP, VP, VP, I32, VP, VP]
+    L.mf_unweight.argtypes = [VP, I64, VP, DBL, U64, U64, I32, VP, I64, VP, VP, VP, VP, VP, VP]
     L.mf_graph_begin.argtypes = [VP, VP]
     L.mf_graph_end.argtypes = [VP, VP, ctypes.POINTER(VP)]
     L.mf_graph_launch.argtypes = [VP, VP]
     L.mf_graph_destroy.argtypes = [VP]
     for f in ('mf_create', 'mf_destroy', 'mf_failures', 'mf_phase_space', 'mf_matrix_element',
               'mf_matrix_element_vjp', 'mf_vegas_refine', 'mf_vegas_refine_noalloc', 'mf_graph_begin',
-              'mf_graph_end', 'mf_graph_launch', 'mf_graph_destroy'):
+              'mf_graph_end', 'mf_graph_launch', 'mf_graph_destroy', 'mf_unweight'):
         getattr(L, f).restype = I32
     _lib = L
     return L
@@ -288,6 +289,33 @@ def mf_vegas_refine_noalloc(prm, n, d, nb, alpha, w, jac, me, pass_, bin_idx, ac
                                          (MF_VEGAS_REFINE if update_edges else 0)
                                          | (MF_VEGAS_ACCUMULATE if accumulate else 0),
                                          _ptr(rng_counter), _stream(stream)))
+
+
+def mf_unweight(h, n, w, w_max=0.0, seed=0, offset=0, p=None, cap=None, idx=None, fac=None, p_out=None,
+                count=None, w_max_out=None, stream=None):
+    """Hit-or-miss unweighting of n weighted events; returns a dict with the output tensors
+    (allocated here when not given; cap defaults to n).  The number kept is count[0]."""
+    dev = torch.device('cuda', h.device)
+    cap = n if cap is None else cap
+    n_ext = 0 if p is None else p.shape[0]
+    idx = idx if idx is not None else torch.empty(max(cap, 1), dtype=torch.int64, device=dev)
+    fac = fac if fac is not None else torch.empty(max(cap, 1), dtype=torch.float64, device=dev)
+    count = count if count is not None else torch.empty(1, dtype=torch.int64, device=dev)
+    w_max_out = w_max_out if w_max_out is not None else torch.empty(1, dtype=torch.float64, device=dev)
+    if p is not None and p_out is None:
+        p_out = torch.empty(n_ext, 4, max(cap, 1), dtype=torch.float64, device=dev)
+    _need(w, n, 'w', torch.float64)
+    _need(p, n_ext * 4 * n, 'p', torch.float64)
+    _need(idx, cap, 'idx', torch.int64)
+    _need(fac, cap, 'fac', torch.float64)
+    _need(p_out, n_ext * 4 * cap, 'p_out', torch.float64)
+    _need(count, 1, 'count', torch.int64)
+    _need(w_max_out, 1, 'w_max_out', torch.float64)
+    if p_out is not None and cap > 0 and p_out.dim() == 3 and p_out.shape[2] != cap:
+        raise ValueError(f'p_out: last dimension {p_out.shape[2]}, need the capacity {cap}')
+    _check(lib().mf_unweight(h.h, n, _ptr(w), float(w_max), seed, offset, n_ext, _ptr(p), cap, _ptr(idx),
+                             _ptr(fac), _ptr(p_out), _ptr(count), _ptr(w_max_out), _stream(stream)))
+    return dict(idx=idx, fac=fac, p_out=p_out, count=count, w_max=w_max_out)
 
 
 class Graph:

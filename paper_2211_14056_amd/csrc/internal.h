@@ -145,6 +145,23 @@ struct VegasArgs {
     uint64_t* rng_counter;      // may be null
 };
 
+struct UnweightArgs {
+    int64_t n;
+    const double* w;            // [n] event weights
+    double w_max;               // reference maximum (> 0), or <= 0: the batch maximum
+    uint64_t seed, offset;      // acceptance stream: counter (offset + e, 0, 1)
+    int n_ext;                  // legs of p / p_out (0: no momenta)
+    const double* p;            // [n_ext][4][n] or null
+    int64_t cap;                // capacity of idx / fac / p_out
+    int64_t* idx;               // [cap] kept event indices, increasing
+    double* fac;                // [cap] weight factors, or null
+    double* p_out;              // [n_ext][4][cap] momenta of the kept events, or null
+    unsigned long long* count;  // device: number of kept events (may exceed cap)
+    double* w_max_out;          // device: the reference maximum used, or null
+    double* work;               // workspace (>= 2049 words)
+};
+hipError_t launch_unweight(const UnweightArgs& a, hipStream_t s);
+
 int vegas_blocks(int64_t n);
 // largest workspace of one Vegas call: at most VEGAS_MAX_BLOCKS blocks, each writing
 // 2 + d * nb <= 2 + 8 * 64 partial sums

@@ -359,6 +359,42 @@ mf_status mf_matrix_element_vjp(mf_handle h, const mf_request* reqs, int n_reqs,
     return MF_OK;
 }
 
+mf_status mf_unweight(mf_handle h, int64_t n, const double* w, double w_max, uint64_t seed, uint64_t offset,
+                      int n_ext, const double* p, int64_t cap, int64_t* idx, double* fac, double* p_out,
+                      uint64_t* count, double* w_max_out, void* stream)
+{
+    g_err.clear();
+    if (!h) return fail(MF_ERR_INVALID_ARG, "mf_unweight: NULL handle");
+    if (n < 0 || n > kMaxEvents) return fail(MF_ERR_INVALID_ARG, "mf_unweight: n outside [0, 2^36]");
+    if (cap < 0) return fail(MF_ERR_INVALID_ARG, "mf_unweight: negative capacity");
+    if (!count) return fail(MF_ERR_INVALID_ARG, "mf_unweight: NULL count");
+    if (n > 0 && !w) return fail(MF_ERR_INVALID_ARG, "mf_unweight: NULL w");
+    if (cap > 0 && !idx) return fail(MF_ERR_INVALID_ARG, "mf_unweight: NULL idx");
+    if (p_out && (!p || n_ext < 1 || n_ext > 8))
+        return fail(MF_ERR_INVALID_ARG, "mf_unweight: p_out needs p and 1 <= n_ext <= 8");
+    if (!(w_max > 0.0) && w_max != 0.0 && !(w_max < 0.0))
+        return fail(MF_ERR_INVALID_ARG, "mf_unweight: w_max is NaN");
+    DeviceGuard g(h->device);
+    mf::UnweightArgs a{};
+    a.n = n;
+    a.w = w;
+    a.w_max = w_max;
+    a.seed = seed;
+    a.offset = offset;
+    a.n_ext = p_out ? n_ext : 0;
+    a.p = p;
+    a.cap = cap;
+    a.idx = idx;
+    a.fac = fac;
+    a.p_out = p_out;
+    a.count = reinterpret_cast<unsigned long long*>(count);
+    a.w_max_out = w_max_out;
+    a.work = h->partials;
+    hipError_t e = mf::launch_unweight(a, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "mf_unweight launch");
+    return MF_OK;
+}
+
 struct mf_graph_s {
     int device = 0;
     hipGraph_t graph = nullptr;
