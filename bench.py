@@ -345,9 +345,10 @@ def _oracle_pass(proc, par, x, edges):
 def cpu_baseline(seed, run_s=7.0):
     """The FP64 oracle (colour-ordered mode) on the host cores, on bounded samples.
 
-    gg -> ttbar gg: one warm-up pass that also sizes the sample, then the median of three
-    timed passes with all threads of the host share, and one pass with a single thread on
-    a sample sized the same way; gg -> ttbar and gg -> ttbar g: one pass each with all
+    gg -> ttbar gg: a warm-up pass, a pass of 2048 events that sizes the sample (about
+    run_s seconds, at most 2e4 events), then the median of three timed passes with all
+    threads of the host share, and one pass with a single thread on a sample sized the same
+    way; gg -> ttbar and gg -> ttbar g: one pass each with all
     threads.  Every pass covers uniforms -> Vegas map -> phase space -> cuts -> |M|^2 ->
     Vegas accumulation.  Returns the record and the first timed sample's (x, |M|^2, pass)
     for the direct comparison of the GPU kernels with the oracle."""
@@ -357,8 +358,10 @@ def cpu_baseline(seed, run_s=7.0):
     torch.set_num_threads(threads)
     d = processes.dims(PROC)
     edges = ovegas.uniform_grid(d, NB)
-    n0 = 256
-    dt0, _, _ = _oracle_pass(PROC, par, philox.uniforms(seed, n0, d), edges)     # warm-up
+    # warm-up (first-call costs), then size the sample from a pass of 2048 events
+    _oracle_pass(PROC, par, philox.uniforms(seed, 512, d), edges)
+    n0 = 2048
+    dt0, _, _ = _oracle_pass(PROC, par, philox.uniforms(seed, n0, d), edges)
     n = int(max(n0, min(20000, n0 * run_s / max(dt0, 1e-3))))
     x = philox.uniforms(seed, n, d)
     times, keep = [], None
@@ -368,8 +371,9 @@ def cpu_baseline(seed, run_s=7.0):
         keep = keep or (x, me, ok)
     t_med = float(np.median(times))
     torch.set_num_threads(1)
-    dt1, _, _ = _oracle_pass(PROC, par, philox.uniforms(seed, n0, d), edges)
-    n1 = int(max(n0, min(20000, n0 * run_s / max(dt1, 1e-3))))
+    m0 = 512
+    dt1, _, _ = _oracle_pass(PROC, par, philox.uniforms(seed, m0, d), edges)
+    n1 = int(max(m0, min(20000, m0 * run_s / max(dt1, 1e-3))))
     dt1, _, _ = _oracle_pass(PROC, par, philox.uniforms(seed + 1, n1, d), edges)
     torch.set_num_threads(threads)
     others = {}
