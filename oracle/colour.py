@@ -62,18 +62,14 @@ def colour_tensor(sigma):
     for pos, g in enumerate(sigma):
         terms.append(letters[g] + idx[pos] + idx[pos + 1])
     spec = ','.join(terms) + '->' + letters + idx[0] + idx[k]
-    return np.einsum(spec, *([T] * k))
+    return np.einsum(spec, *([T] * k), optimize=True)
 
 
 def colour_matrix(k):
     """C[sigma, tau] (float) over the k! orderings of k gluons."""
     perms = orderings(k)
-    X = [colour_tensor(s).reshape(-1) for s in perms]
-    n = len(perms)
-    C = np.zeros((n, n), dtype=np.complex128)
-    for a in range(n):
-        for b in range(n):
-            C[a, b] = np.vdot(X[b], X[a])     # sum X_a X_b^*
+    X = np.stack([colour_tensor(s).reshape(-1) for s in perms])
+    C = X @ X.conj().T                       # C[a, b] = sum over all colours of X_a X_b^*
     assert np.abs(C.imag).max() < 1e-12
     return C.real
 

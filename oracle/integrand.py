@@ -8,7 +8,7 @@ Jacobian multiplies F in the Vegas driver.
 import numpy as np
 import torch
 
-from . import me_explicit, me_ordered
+from . import me_explicit, me_ordered, me_quarks
 from .closed_forms import GEV2_TO_PB
 from .cuts import passes
 from .phase_space import phase_space, incoming
@@ -23,9 +23,13 @@ def momenta(proc, params, u):
 
 
 def me(proc, p, params):
-    """ME per event: explicit diagrams for e+e- -> mu+mu-, colour-ordered form for QCD."""
-    if PROCESSES[proc]['kind'] == 'ee':
+    """ME per event: explicit diagrams for e+e- -> mu+mu-, colour-ordered form for gg-initiated
+    QCD, explicit colour for the processes with two quark lines."""
+    kind = PROCESSES[proc]['kind']
+    if kind == 'ee':
         return me_explicit.matrix_element(proc, p, params)
+    if kind == 'qcd4':
+        return me_quarks.matrix_element(proc, p, params)
     return me_ordered.matrix_element(proc, p, params)
 
 

@@ -131,7 +131,14 @@ def partial_amplitudes(p, hel, params, ward=None):
     return torch.stack(amps, -1)
 
 
-_CMAT = {k: torch.tensor(colour.colour_matrix(k), dtype=torch.float64) for k in (2, 3, 4)}
+_CMAT = {}
+
+
+def colour_matrix(k):
+    """Brute-force colour matrix of k gluons as a tensor (computed once per k)."""
+    if k not in _CMAT:
+        _CMAT[k] = torch.tensor(colour.colour_matrix(k), dtype=torch.float64)
+    return _CMAT[k]
 
 
 def matrix_element(proc, p, params, hel_list=None, return_per_helicity=False):
@@ -139,7 +146,7 @@ def matrix_element(proc, p, params, hel_list=None, return_per_helicity=False):
     info = PROCESSES[proc]
     assert info['kind'] == 'qcd'
     k = info['n_ext'] - 2
-    C = _CMAT[k].to(C128)
+    C = colour_matrix(k).to(C128)
     hels = hel_list if hel_list is not None else helicities(proc)
     tot = torch.zeros(p.shape[0], dtype=torch.float64)
     per = []

@@ -13,6 +13,8 @@ Conventions (readings the paper leaves open):
 * particles are emitted in the order of the ``masses`` list; for the gg
   processes that is t, tbar, then the final gluons;
 * the two incoming partons run along +z and -z with E = sqrt(s)/2 each;
+* sqrt(s) is one value for all events or a tensor with one value per event
+  (hadronic events, whose partonic energy varies);
 * the weight is the phase-space measure
   dPhi_n = (2pi)^4 delta^4(P - sum p) prod d^3p/((2pi)^3 2E)  per point.
 
@@ -33,6 +35,14 @@ def massless_volume(n, s):
     """Volume of massless n-body phase space at c.m. energy squared s."""
     return (TWO_PI ** (4 - 3 * n) * (math.pi / 2.0) ** (n - 1) * s ** (n - 2)
             / (math.factorial(n - 1) * math.factorial(n - 2)))
+
+
+def _per_event(sqrt_s, N):
+    """sqrt(s) as a [N] float64 tensor: one value for all events, or one per event (the
+    partonic energy of hadronic events)."""
+    if torch.is_tensor(sqrt_s):
+        return sqrt_s.to(torch.float64).expand(N).clone() if sqrt_s.dim() == 0 else sqrt_s.to(torch.float64)
+    return torch.full((N,), float(sqrt_s), dtype=torch.float64)
 
 
 def _bisect(f, lo, hi, iters=200):
@@ -75,13 +85,14 @@ def rambo_diet_massless(u, sqrt_s):
     N, d = u.shape
     n = (d + 4) // 3
     assert 3 * n - 4 == d and n >= 2
-    M = [torch.full((N,), float(sqrt_s), dtype=torch.float64)]
+    rs = _per_event(sqrt_s, N)
+    M = [rs]
     for i in range(2, n):
         r = _mass_ratio(u[:, i - 2], n - i)
         M.append(r * M[-1])
     M.append(torch.zeros(N, dtype=torch.float64))   # M_n = 0
     Q = torch.zeros(N, 4, dtype=torch.float64)
-    Q[:, 0] = sqrt_s
+    Q[:, 0] = rs
     ps = []
     for i in range(1, n):
         Mi, Mn = M[i - 1], M[i]
@@ -98,7 +109,7 @@ def rambo_diet_massless(u, sqrt_s):
         ps.append(p_lab)
     ps.append(Q)
     p = torch.stack(ps, 1)
-    w = torch.full((N,), massless_volume(n, float(sqrt_s) ** 2), dtype=torch.float64)
+    w = massless_volume(n, rs * rs)
     return p, w
 
 
@@ -145,11 +156,12 @@ def phase_space(u, sqrt_s, masses):
 
 
 def incoming(N, sqrt_s):
-    """Two incoming massless partons along +z and -z, [N, 2, 4]."""
-    E = 0.5 * sqrt_s
-    a = torch.tensor([E, 0.0, 0.0, E], dtype=torch.float64)
-    b = torch.tensor([E, 0.0, 0.0, -E], dtype=torch.float64)
-    return torch.stack([a, b], 0).unsqueeze(0).expand(N, 2, 4).clone()
+    """Two incoming massless partons along +z and -z, [N, 2, 4] (sqrt_s one value or [N])."""
+    E = 0.5 * _per_event(sqrt_s, N)
+    z = torch.zeros(N, dtype=torch.float64)
+    a = torch.stack([E, z, z, E], -1)
+    b = torch.stack([E, z, z, -E], -1)
+    return torch.stack([a, b], 1)
 
 
 def classic_rambo(u, sqrt_s):
