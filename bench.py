@@ -25,8 +25,9 @@ passes the cuts and against the FP64 CPU oracle on the cpu_baseline sample, and 
 Beside the headline the JSON line carries `extras`: the derivative (VJP) on the
 gg -> ttbar g configuration (4e6 events, FP32 and FP64) and on gg -> ttbar gg
 (2^18 events), the 64-request mixed batch (one persistent launch per process class
-against one launch per request), and the whole mixed Vegas iteration with the
-derivative of its gg -> ttbar gg share, replayed as one library graph.
+against one launch per request), the whole mixed Vegas iteration with the
+derivative of its gg -> ttbar gg share, replayed as one library graph, and hadronic
+gg -> ttbar gg events (parton densities from a toy grid, pp at 13 TeV).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp32_mfma_f32] [--no-extras] [--streams 1|2|3]
 """
@@ -239,8 +240,10 @@ def _best_ms(fn, reps=3):
 
 def extras(mf, h, prm, seed):
     """The other rows of the path, timed beside the headline: the derivative on the
-    gg -> ttbar g configuration (4e6 events) and the 64-request mixed batch in one
-    persistent launch against one launch per request."""
+    gg -> ttbar g configuration (4e6 events) and on gg -> ttbar gg, the 64-request mixed
+    batch in one persistent launch against one launch per request, hadronic events,
+    gg -> ttbar ggg in its three layouts, the quark-initiated processes, and the mixed
+    iteration as one graph."""
     from paper_2211_14056_amd.workloads import mixed_batch
     dev = torch.device('cuda', 0)
     f64 = dict(dtype=torch.float64, device=dev)
@@ -297,6 +300,67 @@ def extras(mf, h, prm, seed):
     out['mixed_batch'] = {'requests': len(spec), 'events': total, 'precision': 'fp32_mfma_bf16',
                           'persistent_ms': tp, 'per_request_ms': ts, 'events_per_s': total / tp * 1e3}
     del reqs, keep
+    # hadronic gg -> ttbar gg events (toy gluon density grid, pp at 13 TeV): density
+    # interpolation + phase space, matrix element, Vegas step, 1e6 events
+    from paper_2211_14056_amd.workloads import toy_pdf_grid
+    grid = mf.PdfGrid(*toy_pdf_grid())
+    pid, n = mf.MF_GG_TTGG, 1_000_000
+    d = mf.mf_process_dims(pid) + 2
+    sqS = 13000.0
+    bufs = dict(p=torch.empty(6, 4, n, **f64), w=torch.empty(n, **f64), jac=torch.empty(n, **f64),
+                pas=torch.empty(n, dtype=torch.uint8, device=dev), bins=torch.empty(d, n, dtype=torch.int16, device=dev),
+                me=torch.empty(n, dtype=torch.float32, device=dev))
+    ed = torch.tensor(np.tile(np.linspace(0, 1, NB + 1), (d, 1)), **f64).contiguous()
+    acc = torch.zeros(2 + d * NB, **f64)
+    vprm = mf.params(sqrt_s=sqS)
+    req = [mf.make_request(pid, bufs['p'], bufs['me'])]
+
+    def ps_pp():
+        mf.mf_phase_space_pp(h, pid, prm, sqS, grid, n, seed=seed, edges=ed, nb=NB, p=bufs['p'], w=bufs['w'],
+                             pass_=bufs['pas'], bin_idx=bufs['bins'], jac=bufs['jac'])
+
+    def path_pp():
+        ps_pp()
+        mf.mf_matrix_element(h, req, mf.MF_FP32_MFMA_BF16, prm)
+        mf.mf_vegas_refine(h, vprm, n, d, NB, 1.5, bufs['w'], bufs['jac'], bufs['me'], bufs['pas'], bufs['bins'],
+                           acc, ed, update_edges=False)
+    t_ps = _best_ms(ps_pp)
+    t_all = _best_ms(path_pp)
+    out['hadronic_gg_ttgg'] = {'events': n, 'sqrt_S_GeV': sqS, 'pdf': 'toy gluon grid 121 x 61 (ln x, ln Q^2)',
+                               'precision': 'fp32_mfma_bf16', 'phase_space_and_pdf_ms': t_ps, 'path_ms': t_all,
+                               'events_per_s': n / t_all * 1e3}
+    del bufs, req
+    # gg -> ttbar ggg: the table-driven recursion, one wavefront per event; 2^18 events per
+    # launch for each precision and lanes-per-event layout
+    pid, n = mf.MF_GG_TTGGG, 1 << 18
+    p = mf.mf_phase_space(h, pid, prm, n, seed=seed)['p']
+    layouts = {}
+    for name, bprec in (('fp64', mf.MF_FP64), ('fp32', mf.MF_FP32)):
+        fl = flops_per_event('gg_ttggg', name)
+        me = torch.empty(n, dtype=torch.float64 if bprec == mf.MF_FP64 else torch.float32, device=dev)
+        req = [mf.make_request(pid, p, me)]
+        for lpe in (16, 32, 64):
+            h.set_launch(proc=pid, precision=bprec, block=lpe)
+            t = _best_ms(lambda: mf.mf_matrix_element(h, req, bprec, prm))
+            layouts[f'{name}_lanes{lpe}'] = {'ms': t, 'events_per_s': n / t * 1e3, 'tflops': n * fl / t * 1e-9}
+        h.set_launch(proc=pid, precision=bprec, block=0)
+    out['me_gg_ttggg'] = {'events': n, 'flops_per_event': fl, 'layouts': layouts}
+    del p, me, req
+    # the quark-initiated processes (generated diagram code, one lane per event), 10^6 events
+    quark = {}
+    for name in ('qq_tt', 'qq_ttg', 'qq_ttgg', 'qg_ttq', 'qg_ttqg'):
+        pid, n = mf.PROCESS[name], 1_000_000
+        p = mf.mf_phase_space(h, pid, prm, n, seed=seed)['p']
+        row = {}
+        for pname, bprec in (('fp64', mf.MF_FP64), ('fp32', mf.MF_FP32)):
+            fl = flops_per_event(name, pname)
+            me = torch.empty(n, dtype=torch.float64 if bprec == mf.MF_FP64 else torch.float32, device=dev)
+            req = [mf.make_request(pid, p, me)]
+            t = _best_ms(lambda: mf.mf_matrix_element(h, req, bprec, prm))
+            row[pname] = {'ms': t, 'events_per_s': n / t * 1e3, 'tflops': n * fl / t * 1e-9}
+        quark[name] = {'events': n, 'flops_per_event': flops_per_event(name, 'fp64'), **row}
+        del p, me, req
+    out['me_quark_processes'] = quark
     # the whole mixed iteration (phase space, matrix elements, derivative of the gg -> ttbar gg
     # share, Vegas per request) as one library graph
     from paper_2211_14056_amd.mixed import MixedIteration

@@ -50,9 +50,23 @@ typedef enum {
  *   MF_GG_TT   : g g -> t tbar
  *   MF_GG_TTG  : g g -> t tbar g
  *   MF_GG_TTGG : g g -> t tbar g g
- * The gg processes are the gluon-initiated channels of the paper's
- * benchmarks (pp -> t tbar (+ g, + g g); sect. 3, Table 1, Figs. 3 and 4). */
-typedef enum { MF_EE_MUMU = 0, MF_GG_TT = 1, MF_GG_TTG = 2, MF_GG_TTGG = 3 } mf_process;
+ *   MF_GG_TTGGG: g g -> t tbar g g g (matrix element by the table-driven recursion, one
+ *                wavefront per event; MF_FP64 and MF_FP32; no derivative, no persistent batch)
+ *   MF_QQ_TT   : q(in) qbar(in) -> t tbar
+ *   MF_QQ_TTG  : q qbar -> t tbar g
+ *   MF_QQ_TTGG : q qbar -> t tbar g g
+ *   MF_QG_TTQ  : q(in) g(in) -> t tbar q(out)
+ *   MF_QG_TTQG : q g -> t tbar q g
+ *                (q a massless light quark of one flavour; matrix elements from generated
+ *                diagram code, one lane per event; MF_FP64 and MF_FP32; no derivative, no
+ *                persistent batch)
+ * The gg processes are the gluon-initiated channels of the paper's benchmarks
+ * (pp -> t tbar (+ g, + g g); sect. 3, Table 1, Figs. 3 and 4), the qq and qg ones its
+ * quark-initiated channels. */
+typedef enum {
+    MF_EE_MUMU = 0, MF_GG_TT = 1, MF_GG_TTG = 2, MF_GG_TTGG = 3, MF_GG_TTGGG = 4,
+    MF_QQ_TT = 5, MF_QQ_TTG = 6, MF_QQ_TTGG = 7, MF_QG_TTQ = 8, MF_QG_TTQG = 9
+} mf_process;
 
 /* Arithmetic of the matrix element.
  *   MF_FP64           : everything in FP64; output f64.
@@ -64,9 +78,9 @@ typedef enum { MF_EE_MUMU = 0, MF_GG_TT = 1, MF_GG_TTG = 2, MF_GG_TTGG = 3 } mf_
 typedef enum { MF_FP64 = 0, MF_FP32 = 1, MF_FP32_MFMA_BF16 = 2, MF_FP32_MFMA_F32 = 3 } mf_precision;
 
 /* Physics and generation-cut parameters (GeV units).  alpha is used by
- * MF_EE_MUMU only, m_t / alpha_s / cuts by the gg processes.  Cuts apply to
- * final-state gluons: pT > pt_min, |eta| < eta_max, and Delta R > dr_min
- * between the two final gluons of MF_GG_TTGG. */
+ * MF_EE_MUMU only, m_t / alpha_s / cuts by the QCD processes.  Cuts apply to
+ * the final-state light partons (gluons and the light quark): pT > pt_min,
+ * |eta| < eta_max, and Delta R > dr_min between every pair of them. */
 typedef struct {
     double sqrt_s, m_t, alpha_s, alpha, pt_min, eta_max, dr_min;
 } mf_params;
@@ -100,7 +114,7 @@ typedef struct {
 typedef struct mf_handle_s* mf_handle;
 
 /* Create a handle bound to HIP device `device`; it owns workspace (Vegas
- * reduction partials, about 4.2 MB, the largest any call needs; the Newton
+ * reduction partials, about 8.4 MB, the largest any call needs; the Newton
  * failure counter; the tile counter of persistent launches), all allocated
  * here, so no other call allocates, frees or synchronises the device.
  * One handle per thread; calls on one handle from several host threads must
@@ -129,7 +143,8 @@ int mf_process_dims(int proc);
  *     related by swapping both the beams and the final gluons, currents and
  *     amplitudes exchanged within the pair), 256 = four lanes per event
  *     (orderings split by first gluon, currents shared within the quad),
- *     64 or 192 = one lane per event.
+ *     64 or 192 = one lane per event.  For gg -> ttbar ggg the value is the number of
+ *     lanes that share an event: 16, 32 or 64 (0, the default: 64).
  *     proc < 0 leaves the per-process settings unchanged.
  *   batch_waves_per_cu >= 0: one-wave blocks per compute unit in each
  *     persistent launch (0, the default: as many as the process's kernel fits);
@@ -178,9 +193,13 @@ mf_status mf_phase_space(mf_handle h, int proc, const mf_params* prm, int64_t n,
  * of each event of each request (sect. 2: the matrix element the paper's
  * generated code evaluates per event).  With n_reqs > 1 and batch_persistent
  * set, the gg requests are served by one persistent launch per process class
- * (mf_set_launch); otherwise one launch per request.
+ * (mf_set_launch); otherwise one launch per request.  MF_GG_TTGGG requests
+ * always take a launch of their own (the table-driven recursion, one wavefront
+ * per event; mf_set_launch's block sets its lanes per event).
  * Errors: MF_ERR_INVALID_ARG for n_reqs < 1, NULL reqs/prm, a bad process or
- * precision, n < 0, or NULL p / me_out with n > 0.
+ * precision, n < 0, or NULL p / me_out with n > 0; MF_ERR_UNSUPPORTED for
+ * the matrix-core precisions with MF_EE_MUMU or MF_GG_TTGGG.  Every error is
+ * found before anything is launched.
  */
 mf_status mf_matrix_element(mf_handle h, const mf_request* reqs, int n_reqs, int precision,
                             const mf_params* prm, void* stream);
@@ -197,14 +216,14 @@ mf_status mf_matrix_element(mf_handle h, const mf_request* reqs, int n_reqs, int
  * f32 otherwise).  The requests of one process are served by one launch (a
  * grid of 64-event tiles over up to 32 requests); all requests share `edges`.
  * Errors: as mf_matrix_element, plus NULL x / grad_me / grad_x / grad_theta,
- * MF_ERR_UNSUPPORTED for MF_EE_MUMU.
+ * MF_ERR_UNSUPPORTED for MF_EE_MUMU and MF_GG_TTGGG.
  */
 mf_status mf_matrix_element_vjp(mf_handle h, const mf_request* reqs, int n_reqs, int precision,
                                 const mf_params* prm, const double* edges, int nb, void* stream);
 
 /*
  * mf_vegas_refine -- the Vegas step (sect. 1): forms F = flux * w * jac * me (events
- * that pass the cuts and have w > 0; 0 otherwise) with
+ * that pass the cuts and have a weight that is neither 0 nor NaN; 0 otherwise) with
  * flux = (hbar c)^2 / (2 s) in pb GeV^2 / GeV^2 (so F is in pb), reduces
  * acc[0] = sum F, acc[1] = sum F^2, acc[2 + k*nb + i] = sum of F^2 over events
  * in bin i of dimension k (deterministic order).  flags:
@@ -215,11 +234,12 @@ mf_status mf_matrix_element_vjp(mf_handle h, const mf_request* reqs, int n_reqs,
  * If rng_counter is not NULL, *rng_counter += n on the device.
  *   w, me      [n] required (me is f32 when me_f32 != 0); jac, pass optional;
  *   bin_idx    [d][n] required; F [n] optional output; acc [2 + d*nb] out.
- * Errors: MF_ERR_INVALID_ARG for d < 1 or d > 8, nb < 2 or nb > 64, n < 0,
+ * Errors: MF_ERR_INVALID_ARG for d < 1 or d > 16, nb < 2 or nb > 64, n < 0,
  * or a NULL required pointer.  It uses the handle's workspace (allocated by
  * mf_create) and allocates nothing.  F = 0 exactly for an event that fails the
- * cuts or has w <= 0 (a failed phase-space solve, NaN uniforms), whatever its
- * |M|^2; a dimension whose histogram holds a non-finite value keeps its grid.
+ * cuts or has w = 0 or NaN (a failed phase-space solve, NaN uniforms), whatever its
+ * |M|^2; a negative weight counts as it is; a dimension whose histogram holds a
+ * non-finite value keeps its grid.
  */
 enum { MF_VEGAS_REFINE = 1, MF_VEGAS_ACCUMULATE = 2 };
 
@@ -234,8 +254,8 @@ mf_status mf_vegas_refine(mf_handle h, const mf_params* prm, int64_t n, int d, i
  * allocation): mf_vegas_refine without a handle and without any allocation.
  * Same arguments, results and errors as mf_vegas_refine (bit-identical
  * results), on the CURRENT device, which `stream` must belong to.  The block
- * partials live in a static device array of the library: 1024 x 514 doubles
- * (4.2 MB), one copy per device, held until the process ends; every valid
+ * partials live in a static device array of the library: 1024 x 1026 doubles
+ * (8.4 MB), one copy per device, held until the process ends; every valid
  * (n, d, nb) fits, and a size that would not is rejected with
  * MF_ERR_INVALID_ARG.  All calls on one device share that array: calls that
  * overlap on one GPU (several streams or host threads) race and give wrong
@@ -245,6 +265,54 @@ mf_status mf_vegas_refine_noalloc(const mf_params* prm, int64_t n, int d, int nb
                                   const double* w, const double* jac, const void* me, int me_f32,
                                   const uint8_t* pass, const int16_t* bin_idx, double* F, double* acc,
                                   double* edges, int flags, uint64_t* rng_counter, void* stream);
+
+/*
+ * Hadronic events (the paper's workload is pp -> t tbar + jets; sect. 3, Table 1): the
+ * partonic processes weighted with parton densities interpolated from a grid (the step
+ * before the matrix element, sect. 1).  Built for the gluon-gluon channel.
+ *
+ * mf_pdf_grid: a tabulated density, device arrays owned by the caller:
+ *   log_x [nx], log_q2 [nq]  increasing nodes in ln x and ln Q^2 (nx, nq >= 2);
+ *   xf    [nq][nx]           x f(x, Q^2) at the nodes.
+ * Interpolation: cubic Hermite in ln x (per Q^2 node), then in ln Q^2 over the nodes
+ * j-1 .. j+2 around the cell; node slopes are the mean of the adjacent secant slopes
+ * (one secant at the grid ends); points outside the grid take the edge values.
+ */
+typedef struct {
+    int32_t nx, nq;
+    const double* log_x;
+    const double* log_q2;
+    const double* xf;
+} mf_pdf_grid;
+
+/* x f(x, Q^2) for n points: x [n], q2 [n] (GeV^2), xf_out [n].
+ * Errors: MF_ERR_INVALID_ARG for a NULL or too small grid, n outside [0, 2^36], NULL arrays. */
+mf_status mf_pdf_eval(mf_handle h, const mf_pdf_grid* g, int64_t n, const double* x, const double* q2,
+                      double* xf_out, void* stream);
+
+/*
+ * mf_phase_space_pp -- events of one parton channel of pp collisions at sqrt_S (GeV):
+ * parton 1 from beam 1 (+z) with density grid g, parton 2 from beam 2 with density
+ * grid g_b (NULL: g as well); for example gg -> t tbar (+ g ...) with the gluon for
+ * both, q qbar -> t tbar (+ g ...) with a quark and an antiquark density, q g -> t tbar q
+ * (+ g) with a quark and the gluon.  As mf_phase_space with d + 2 uniforms per event,
+ * (u_tau, u_y, then the partonic d):
+ *   tau = tau0^(1 - u_tau), tau0 = (2 m_t)^2 / S;  y = (u_y - 1/2) ln(1/tau);
+ *   x1 = sqrt(tau) e^y, x2 = sqrt(tau) e^-y, s_hat = tau S;
+ * the partonic event is generated in its c.m. frame at sqrt(s_hat) (p: parton 1 along +z,
+ * E = sqrt(s_hat)/2); the cuts are applied in the lab frame (light-parton pseudorapidities + y);
+ *   w = tau ln(1/tau0) ln(1/tau) f_a(x1, m_t^2) f_b(x2, m_t^2) W(s_hat) S / s_hat,
+ * so that mf_vegas_refine called with sqrt_s = sqrt_S forms the hadronic integrand
+ * (hbar c)^2 / (2 s_hat) J f f W |M|^2 Theta.  edges, bin_idx, x_out have d + 2 rows;
+ * x12 [2][n] (x1, x2) optional.  The factorisation scale is m_t.
+ * Errors: MF_ERR_INVALID_ARG for MF_EE_MUMU, NULL params, a bad grid, n outside
+ * [0, 2^36], NULL p or w, nb outside [2, 64] with edges or bin_idx, unless
+ * 0 < 2 m_t < sqrt_S.
+ */
+mf_status mf_phase_space_pp(mf_handle h, int proc, const mf_params* prm, double sqrt_S, const mf_pdf_grid* g,
+                            const mf_pdf_grid* g_b, int64_t n, const double* x, uint64_t seed, uint64_t offset, const uint64_t* offset_dev,
+                            const double* edges, int nb, double* p, double* w, uint8_t* pass, int16_t* bin_idx,
+                            double* jac, double* x_out, double* x12, void* stream);
 
 /*
  * mf_unweight -- unit-weight event sample from weighted events (hit-or-miss;

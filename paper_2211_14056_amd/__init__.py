@@ -15,8 +15,11 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, 'libmfhip.so')
 
-MF_EE_MUMU, MF_GG_TT, MF_GG_TTG, MF_GG_TTGG = 0, 1, 2, 3
-PROCESS = {'ee_mumu': MF_EE_MUMU, 'gg_tt': MF_GG_TT, 'gg_ttg': MF_GG_TTG, 'gg_ttgg': MF_GG_TTGG}
+MF_EE_MUMU, MF_GG_TT, MF_GG_TTG, MF_GG_TTGG, MF_GG_TTGGG = 0, 1, 2, 3, 4
+MF_QQ_TT, MF_QQ_TTG, MF_QQ_TTGG, MF_QG_TTQ, MF_QG_TTQG = 5, 6, 7, 8, 9
+PROCESS = {'ee_mumu': MF_EE_MUMU, 'gg_tt': MF_GG_TT, 'gg_ttg': MF_GG_TTG, 'gg_ttgg': MF_GG_TTGG,
+           'gg_ttggg': MF_GG_TTGGG, 'qq_tt': MF_QQ_TT, 'qq_ttg': MF_QQ_TTG, 'qq_ttgg': MF_QQ_TTGG,
+           'qg_ttq': MF_QG_TTQ, 'qg_ttqg': MF_QG_TTQG}
 MF_FP64, MF_FP32, MF_FP32_MFMA_BF16, MF_FP32_MFMA_F32 = 0, 1, 2, 3
 PRECISION = {'fp64': MF_FP64, 'fp32': MF_FP32, 'fp32_mfma_bf16': MF_FP32_MFMA_BF16,
              'fp32_mfma_f32': MF_FP32_MFMA_F32}
@@ -40,6 +43,11 @@ class mf_request(ctypes.Structure):
     _fields_ = [('proc', ctypes.c_int32), ('reserved', ctypes.c_int32), ('n', ctypes.c_int64),
                 ('p', ctypes.c_void_p), ('me_out', ctypes.c_void_p), ('x', ctypes.c_void_p),
                 ('grad_me', ctypes.c_void_p), ('grad_x', ctypes.c_void_p), ('grad_theta', ctypes.c_void_p)]
+
+
+class mf_pdf_grid(ctypes.Structure):
+    _fields_ = [('nx', ctypes.c_int32), ('nq', ctypes.c_int32), ('log_x', ctypes.c_void_p),
+                ('log_q2', ctypes.c_void_p), ('xf', ctypes.c_void_p)]
 
 
 _lib = None
@@ -73,13 +81,18 @@ def lib():
     L.mf_vegas_refine_noalloc.argtypes = [ctypes.POINTER(mf_params), I64, I32, I32, DBL, VP, VP, VP, I32, VP,
                                           VP, VP, VP, VP, I32, VP, VP]
     L.mf_unweight.argtypes = [VP, I64, VP, DBL, U64, U64, I32, VP, I64, VP, VP, VP, VP, VP, VP]
+    L.mf_pdf_eval.argtypes = [VP, ctypes.POINTER(mf_pdf_grid), I64, VP, VP, VP, VP]
+    L.mf_phase_space_pp.argtypes = [VP, I32, ctypes.POINTER(mf_params), DBL, ctypes.POINTER(mf_pdf_grid),
+                                    ctypes.POINTER(mf_pdf_grid), I64, VP, U64, U64, VP, VP, I32, VP, VP, VP, VP,
+                                    VP, VP, VP, VP]
     L.mf_graph_begin.argtypes = [VP, VP]
     L.mf_graph_end.argtypes = [VP, VP, ctypes.POINTER(VP)]
     L.mf_graph_launch.argtypes = [VP, VP]
     L.mf_graph_destroy.argtypes = [VP]
     for f in ('mf_create', 'mf_destroy', 'mf_failures', 'mf_phase_space', 'mf_matrix_element',
               'mf_matrix_element_vjp', 'mf_vegas_refine', 'mf_vegas_refine_noalloc', 'mf_graph_begin',
-              'mf_graph_end', 'mf_graph_launch', 'mf_graph_destroy', 'mf_unweight'):
+              'mf_graph_end', 'mf_graph_launch', 'mf_graph_destroy', 'mf_unweight', 'mf_pdf_eval',
+              'mf_phase_space_pp'):
         getattr(L, f).restype = I32
     _lib = L
     return L
@@ -289,6 +302,60 @@ def mf_vegas_refine_noalloc(prm, n, d, nb, alpha, w, jac, me, pass_, bin_idx, ac
                                          (MF_VEGAS_REFINE if update_edges else 0)
                                          | (MF_VEGAS_ACCUMULATE if accumulate else 0),
                                          _ptr(rng_counter), _stream(stream)))
+
+
+class PdfGrid:
+    """A tabulated density on the device: ln x nodes [nx], ln Q^2 nodes [nq], x f [nq][nx]."""
+
+    def __init__(self, log_x, log_q2, xf, device=None):
+        dev = torch.device('cuda', torch.cuda.current_device() if device is None else device)
+        self.log_x = torch.as_tensor(log_x, dtype=torch.float64).to(dev).contiguous()
+        self.log_q2 = torch.as_tensor(log_q2, dtype=torch.float64).to(dev).contiguous()
+        self.xf = torch.as_tensor(xf, dtype=torch.float64).to(dev).contiguous()
+        nx, nq = self.log_x.numel(), self.log_q2.numel()
+        if self.xf.numel() != nx * nq:
+            raise ValueError(f'xf: {self.xf.numel()} values, need {nq} x {nx}')
+        self.c = mf_pdf_grid(nx, nq, self.log_x.data_ptr(), self.log_q2.data_ptr(), self.xf.data_ptr())
+
+
+def mf_pdf_eval(h, grid, x, q2, out=None, stream=None):
+    """x f(x, Q^2) for the points x [n], q2 [n]."""
+    n = x.numel()
+    out = out if out is not None else torch.empty(n, dtype=torch.float64, device=x.device)
+    _need(q2, n, 'q2', torch.float64)
+    _need(out, n, 'out', torch.float64)
+    if x.dtype != torch.float64:
+        raise ValueError('x: need torch.float64')
+    _check(lib().mf_pdf_eval(h.h, ctypes.byref(grid.c), n, _ptr(x), _ptr(q2), _ptr(out), _stream(stream)))
+    return out
+
+
+def mf_phase_space_pp(h, proc, prm, sqrt_S, grid, n, x=None, seed=0, offset=0, offset_dev=None, edges=None,
+                      nb=50, p=None, w=None, pass_=None, bin_idx=None, jac=None, x_out=None, x12=None,
+                      stream=None, grid_b=None):
+    """Events of one parton channel of pp collisions (d + 2 uniforms per event): parton 1 with
+    density `grid`, parton 2 with `grid_b` (None: `grid`); returns a dict of outputs."""
+    dev = torch.device('cuda', h.device)
+    n_ext = mf_process_legs(proc)
+    d = mf_process_dims(proc) + 2
+    f64 = dict(dtype=torch.float64, device=dev)
+    p = p if p is not None else torch.empty(n_ext, 4, n, **f64)
+    w = w if w is not None else torch.empty(n, **f64)
+    _need(p, n_ext * 4 * n, 'p', torch.float64)
+    _need(w, n, 'w', torch.float64)
+    _need(x, d * n, 'x', torch.float64)
+    _need(edges, d * (nb + 1), 'edges', torch.float64)
+    _need(pass_, n, 'pass', torch.uint8)
+    _need(bin_idx, d * n, 'bin_idx', torch.int16)
+    _need(jac, n, 'jac', torch.float64)
+    _need(x_out, d * n, 'x_out', torch.float64)
+    _need(x12, 2 * n, 'x12', torch.float64)
+    _need(offset_dev, 1, 'offset_dev', torch.int64)
+    gb = ctypes.byref(grid_b.c) if grid_b is not None else None
+    _check(lib().mf_phase_space_pp(h.h, proc, ctypes.byref(prm), float(sqrt_S), ctypes.byref(grid.c), gb, n, _ptr(x),
+                                   seed, offset, _ptr(offset_dev), _ptr(edges), nb, _ptr(p), _ptr(w), _ptr(pass_),
+                                   _ptr(bin_idx), _ptr(jac), _ptr(x_out), _ptr(x12), _stream(stream)))
+    return dict(p=p, w=w, pass_=pass_, bin_idx=bin_idx, jac=jac, x=x_out if x_out is not None else x, x12=x12)
 
 
 def mf_unweight(h, n, w, w_max=0.0, seed=0, offset=0, p=None, cap=None, idx=None, fac=None, p_out=None,

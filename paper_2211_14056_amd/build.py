@@ -17,7 +17,8 @@ BUILD = os.path.join(HERE, '_build')
 
 SOURCES = ['me_vjp_ttgg_f64.hip', 'me_vjp_ttgg_f32.hip', 'me_batch_f64.hip', 'me_batch_mfma.hip', 'me_batch_f32.hip',
            'me_vjp_small.hip', 'me_kernels.hip', 'me_mfma.hip', 'mf_api.cpp', 'phase_space.hip', 'me_vjp.hip',
-           'me_batch.hip', 'vegas.hip', 'me_ttgg_quad.hip', 'me_ttgg_pair.hip', 'unweight.hip']
+           'me_batch.hip', 'vegas.hip', 'me_ttgg_quad.hip', 'me_ttgg_pair.hip', 'unweight.hip', 'hadronic.hip', 'me_bg.hip',
+           'me_quark.hip']
 
 FLAGS = ['--offload-arch=gfx950', '-O3', '-std=c++17', '-fPIC', '-ffp-contract=fast',
          # no packed FP32 arithmetic anywhere in device code

@@ -6,9 +6,22 @@
 
 namespace mf {
 
-enum Proc { EE_MUMU = 0, GG_TT = 1, GG_TTG = 2, GG_TTGG = 3, NPROC = 4 };
+enum Proc {
+    EE_MUMU = 0, GG_TT = 1, GG_TTG = 2, GG_TTGG = 3, GG_TTGGG = 4,
+    QQ_TT = 5, QQ_TTG = 6, QQ_TTGG = 7, QG_TTQ = 8, QG_TTQG = 9, NPROC = 10
+};
 
-inline int n_ext(int proc) { return proc == GG_TTG ? 5 : (proc == GG_TTGG ? 6 : 4); }
+inline int n_ext(int proc)
+{
+    switch (proc) {
+    case GG_TTG: case QQ_TTG: case QG_TTQ: return 5;
+    case GG_TTGG: case QQ_TTGG: case QG_TTQG: return 6;
+    case GG_TTGGG: return 7;
+    default: return 4;
+    }
+}
+// processes with two quark lines (the generated diagram kernels of me_quark.hip)
+inline bool quark_proc(int proc) { return proc >= QQ_TT && proc <= QG_TTQG; }
 inline int n_out(int proc) { return n_ext(proc) - 2; }
 inline int dims(int proc) { return 3 * n_out(proc) - 4; }
 inline int n_gluons(int proc) { return proc == EE_MUMU ? 0 : n_ext(proc) - 2; }
@@ -20,7 +33,7 @@ struct PsArgs {
     uint64_t seed, offset;
     const uint64_t* offset_dev; // optional device-side offset added to `offset`
     const double* edges;        // [d][nb+1] or null (identity map)
-    double sqrt_s, m_out[4];
+    double sqrt_s, m_out[5];     // final-state masses, one per outgoing leg (up to 5)
     double pt_min, eta_max, dr_min;
     double* p;                  // [n_ext][4][n]
     double* w;                  // [n]
@@ -51,6 +64,11 @@ hipError_t launch_matrix_element_mfma(const MeJob& j, int precision, double mt, 
                                       hipStream_t s);
 // g g -> t tbar g g in FP64 with four lanes per event; `coupling` = (4 pi alpha_s)^4
 hipError_t launch_ttgg_quad(const MeJob& j, double mt, double coupling, hipStream_t s);
+// g g -> t tbar g g g by the table-driven recursion, lanes_per_event in {16, 32, 64}
+// (0: 64); precision 0 = FP64, 1 = FP32 (FP64 kinematics, FP32 recursion and colour sum)
+hipError_t launch_quark(const MeJob& j, int precision, double mt, double coupling, int block, hipStream_t s);
+hipError_t launch_ttggg(const MeJob& j, int precision, double mt, double coupling, int lanes_per_event,
+                        hipStream_t s);
 // g g -> t tbar g g in FP64 with two lanes per event (the default layout)
 hipError_t launch_ttgg_pair(const MeJob& j, double mt, double coupling, hipStream_t s);
 // launch-configuration values of mf_set_launch that select the layout of g g -> t tbar g g
@@ -145,6 +163,40 @@ struct VegasArgs {
     uint64_t* rng_counter;      // may be null
 };
 
+// tabulated parton density (device arrays): x f at nodes equally or unequally spaced in
+// ln x and ln Q^2
+struct PdfGrid {
+    int nx, nq;
+    const double* lx;      // [nx] ln x nodes, increasing
+    const double* lq;      // [nq] ln Q^2 nodes, increasing
+    const double* v;       // [nq][nx] x f at the nodes
+};
+
+// hadronic (gluon-gluon) events; the uniforms are (u_tau, u_y, partonic ...)
+struct PpArgs {
+    int64_t n;
+    int nb;
+    const double* x;            // [d + 2][n] or null (generate)
+    uint64_t seed, offset;
+    const uint64_t* offset_dev;
+    const double* edges;        // [d + 2][nb + 1] or null
+    double S, tau0, mu2;        // collider energy squared, threshold tau, factorisation scale squared
+    double m_out[5];             // final-state masses, one per outgoing leg (up to 5)
+    double pt_min, eta_max, dr_min;
+    PdfGrid grid, grid_b;       // densities of parton 1 (beam 1) and parton 2 (beam 2)
+    double* p;                  // [n_ext][4][n] partonic c.m. frame
+    double* w;                  // [n]
+    uint8_t* pass;
+    int16_t* bin_idx;           // [d + 2][n] or null
+    double* jac;
+    double* x_out;              // [d + 2][n] or null
+    double* x12;                // [2][n] or null: x1, x2
+    unsigned long long* fail_count;
+};
+hipError_t launch_phase_space_pp(const PpArgs& a, int n_out, hipStream_t s);
+hipError_t launch_pdf_eval(const PdfGrid& g, int64_t n, const double* x, const double* q2, double* out,
+                           hipStream_t s);
+
 struct UnweightArgs {
     int64_t n;
     const double* w;            // [n] event weights
@@ -166,7 +218,8 @@ int vegas_blocks(int64_t n);
 // largest workspace of one Vegas call: at most VEGAS_MAX_BLOCKS blocks, each writing
 // 2 + d * nb <= 2 + 8 * 64 partial sums
 constexpr int VEGAS_MAX_BLOCKS = 1024;
-constexpr int VEGAS_MAX_CELLS = 2 + 8 * 64;
+constexpr int VEGAS_MAX_D = 16;
+constexpr int VEGAS_MAX_CELLS = 2 + VEGAS_MAX_D * 64;
 constexpr size_t VEGAS_PARTIALS_MAX = (size_t)VEGAS_MAX_BLOCKS * VEGAS_MAX_CELLS;
 hipError_t launch_vegas(const VegasArgs& a, hipStream_t s);
 // device address of the library's static block-partials array (VEGAS_PARTIALS_MAX

@@ -169,6 +169,11 @@ hipError_t launch_matrix_element(const MeJob& j, int precision, double mt, doubl
         const double g2 = 4.0 * kPi * alpha_s;
         for (int i = 0; i < n_gluons(j.proc); ++i) coupling *= g2;
     }
+    if (j.proc == GG_TTGGG) {
+        if (precision > 1) return hipErrorInvalidValue;          // no matrix-core colour form
+        return launch_ttggg(j, precision, mt, coupling, block, s);
+    }
+    if (quark_proc(j.proc)) return launch_quark(j, precision, mt, coupling, block, s);
     if (j.proc == GG_TTGG && precision == 0 && block == TTGG_QUAD_LAYOUT)
         return launch_ttgg_quad(j, mt, coupling, s);
     if (j.proc == GG_TTGG && precision == 0 && (block <= 0 || block == TTGG_PAIR_LAYOUT))

@@ -30,7 +30,7 @@ mf_status hip_fail(hipError_t e, const char* where)
     return fail(MF_ERR_HIP, "%s: %s", where, hipGetErrorString(e));
 }
 
-bool valid_proc(int p) { return p >= MF_EE_MUMU && p <= MF_GG_TTGG; }
+bool valid_proc(int p) { return p >= MF_EE_MUMU && p <= MF_QG_TTQG; }
 
 // largest batch a call accepts: keeps every launch grid within 32 bits
 constexpr int64_t kMaxEvents = int64_t(1) << 36;
@@ -44,7 +44,7 @@ struct mf_handle_s {
     unsigned long long* fail_dev = nullptr;
     unsigned* tile_counter = nullptr;  // persistent-batch work queue
     // launch configuration (set by mf_set_launch / the autotuner)
-    int block[4][4];                   // [process][precision] threads per block, 0 = default
+    int block[mf::NPROC][4];           // [process][precision] threads per block, 0 = default
     int batch_waves_per_cu = 0;        // persistent grid = waves_per_cu * n_cu one-wave blocks (0: as many as fit)
     int batch_persistent = 1;          // 0 = one launch per request instead
 };
@@ -139,8 +139,12 @@ mf_status mf_set_launch(mf_handle h, int proc, int precision, int block, int bat
     if (proc >= 0) {
         if (!valid_proc(proc) || precision < MF_FP64 || precision > MF_FP32_MFMA_F32)
             return fail(MF_ERR_INVALID_ARG, "mf_set_launch: bad process or precision");
-        if (block != 0 && (block < 64 || block > 256 || block % 64))
+        if (proc == MF_GG_TTGGG) {
+            if (block != 0 && block != 16 && block != 32 && block != 64)
+                return fail(MF_ERR_INVALID_ARG, "mf_set_launch: lanes per event must be 16, 32 or 64 (0 = default)");
+        } else if (block != 0 && (block < 64 || block > 256 || block % 64)) {
             return fail(MF_ERR_INVALID_ARG, "mf_set_launch: block must be 64, 128, 192 or 256 (0 = default)");
+        }
         h->block[proc][precision] = block;
     }
     if (batch_waves_per_cu >= 0) {
@@ -195,7 +199,7 @@ mf_status mf_phase_space(mf_handle h, int proc, const mf_params* prm, int64_t n,
     a.offset_dev = offset_dev;
     a.edges = edges;
     a.sqrt_s = prm->sqrt_s;
-    for (int i = 0; i < 4; ++i) a.m_out[i] = 0.0;
+    for (int i = 0; i < 5; ++i) a.m_out[i] = 0.0;
     if (qcd) a.m_out[0] = a.m_out[1] = prm->m_t;
     a.pt_min = prm->pt_min;
     a.eta_max = prm->eta_max;
@@ -228,6 +232,12 @@ static mf_status check_requests(const char* who, const mf_request* reqs, int n_r
         if (!vjp && !r.me_out) return fail(MF_ERR_INVALID_ARG, "%s: request %d: NULL me_out", who, i);
         if (vjp && (!r.x || !r.grad_me || !r.grad_x || !r.grad_theta))
             return fail(MF_ERR_INVALID_ARG, "%s: request %d: NULL x/grad_me/grad_x/grad_theta", who, i);
+        // no matrix-core colour form without colour (e+e-), for the table-driven recursion or
+        // for the two-quark-line diagram code, rejected before anything is launched
+        if (!vjp && precision >= MF_FP32_MFMA_BF16
+            && (r.proc == MF_EE_MUMU || r.proc == MF_GG_TTGGG || mf::quark_proc(r.proc)))
+            return fail(MF_ERR_UNSUPPORTED, "%s: request %d: precision %d not available for process %d", who, i,
+                        precision, r.proc);
     }
     return MF_OK;
 }
@@ -307,8 +317,9 @@ mf_status mf_matrix_element_vjp(mf_handle h, const mf_request* reqs, int n_reqs,
     if (edges && (nb < 2 || nb > 64))
         return fail(MF_ERR_INVALID_ARG, "mf_matrix_element_vjp: nb = %d outside [2, 64]", nb);
     for (int i = 0; i < n_reqs; ++i)
-        if (reqs[i].proc == MF_EE_MUMU && reqs[i].n > 0)
-            return fail(MF_ERR_UNSUPPORTED, "mf_matrix_element_vjp: no derivative for MF_EE_MUMU");
+        if ((reqs[i].proc == MF_EE_MUMU || reqs[i].proc == MF_GG_TTGGG || mf::quark_proc(reqs[i].proc))
+            && reqs[i].n > 0)
+            return fail(MF_ERR_UNSUPPORTED, "mf_matrix_element_vjp: no derivative for process %d", reqs[i].proc);
     if (!(2.0 * prm->m_t < prm->sqrt_s && prm->m_t >= 0.0 && prm->alpha_s > 0.0))
         return fail(MF_ERR_INVALID_ARG, "mf_matrix_element_vjp: need 0 <= 2 m_t < sqrt_s and alpha_s > 0");
     DeviceGuard g(h->device);
@@ -356,6 +367,84 @@ mf_status mf_matrix_element_vjp(mf_handle h, const mf_request* reqs, int n_reqs,
         mf_status s2 = flush();
         if (s2 != MF_OK) return s2;
     }
+    return MF_OK;
+}
+
+static mf_status pdf_grid(const char* who, const mf_pdf_grid* g, mf::PdfGrid& out)
+{
+    if (!g) return fail(MF_ERR_INVALID_ARG, "%s: NULL grid", who);
+    if (g->nx < 2 || g->nq < 2) return fail(MF_ERR_INVALID_ARG, "%s: grid needs at least 2 x 2 nodes", who);
+    if (!g->log_x || !g->log_q2 || !g->xf) return fail(MF_ERR_INVALID_ARG, "%s: NULL grid array", who);
+    out = mf::PdfGrid{g->nx, g->nq, g->log_x, g->log_q2, g->xf};
+    return MF_OK;
+}
+
+mf_status mf_pdf_eval(mf_handle h, const mf_pdf_grid* g, int64_t n, const double* x, const double* q2,
+                      double* xf_out, void* stream)
+{
+    g_err.clear();
+    if (!h) return fail(MF_ERR_INVALID_ARG, "mf_pdf_eval: NULL handle");
+    mf::PdfGrid grid;
+    mf_status st = pdf_grid("mf_pdf_eval", g, grid);
+    if (st != MF_OK) return st;
+    if (n < 0 || n > kMaxEvents) return fail(MF_ERR_INVALID_ARG, "mf_pdf_eval: n outside [0, 2^36]");
+    if (n > 0 && (!x || !q2 || !xf_out)) return fail(MF_ERR_INVALID_ARG, "mf_pdf_eval: NULL x, q2 or xf_out");
+    DeviceGuard dg(h->device);
+    hipError_t e = mf::launch_pdf_eval(grid, n, x, q2, xf_out, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "mf_pdf_eval launch");
+    return MF_OK;
+}
+
+mf_status mf_phase_space_pp(mf_handle h, int proc, const mf_params* prm, double sqrt_S, const mf_pdf_grid* g,
+                            const mf_pdf_grid* g_b, int64_t n, const double* x, uint64_t seed, uint64_t offset, const uint64_t* offset_dev,
+                            const double* edges, int nb, double* p, double* w, uint8_t* pass, int16_t* bin_idx,
+                            double* jac, double* x_out, double* x12, void* stream)
+{
+    g_err.clear();
+    if (!h) return fail(MF_ERR_INVALID_ARG, "mf_phase_space_pp: NULL handle");
+    if (!valid_proc(proc) || proc == MF_EE_MUMU)
+        return fail(MF_ERR_INVALID_ARG, "mf_phase_space_pp: process %d is not a QCD process", proc);
+    if (!prm) return fail(MF_ERR_INVALID_ARG, "mf_phase_space_pp: NULL params");
+    mf::PdfGrid grid, grid_b;
+    mf_status st = pdf_grid("mf_phase_space_pp", g, grid);
+    if (st != MF_OK) return st;
+    st = pdf_grid("mf_phase_space_pp", g_b ? g_b : g, grid_b);
+    if (st != MF_OK) return st;
+    if (n < 0 || n > kMaxEvents) return fail(MF_ERR_INVALID_ARG, "mf_phase_space_pp: n outside [0, 2^36]");
+    if (n == 0) return MF_OK;
+    if (!p || !w) return fail(MF_ERR_INVALID_ARG, "mf_phase_space_pp: NULL p or w");
+    if ((edges || bin_idx) && (nb < 2 || nb > 64))
+        return fail(MF_ERR_INVALID_ARG, "mf_phase_space_pp: nb = %d outside [2, 64]", nb);
+    if (!(prm->m_t > 0.0) || !(sqrt_S > 2.0 * prm->m_t))
+        return fail(MF_ERR_INVALID_ARG, "mf_phase_space_pp: need 0 < 2 m_t < sqrt_S");
+    DeviceGuard dg(h->device);
+    mf::PpArgs a{};
+    a.n = n;
+    a.nb = nb;
+    a.x = x;
+    a.seed = seed;
+    a.offset = offset;
+    a.offset_dev = offset_dev;
+    a.edges = edges;
+    a.S = sqrt_S * sqrt_S;
+    a.tau0 = 4.0 * prm->m_t * prm->m_t / a.S;
+    a.mu2 = prm->m_t * prm->m_t;
+    for (int i = 0; i < 5; ++i) a.m_out[i] = i < 2 ? prm->m_t : 0.0;
+    a.pt_min = prm->pt_min;
+    a.eta_max = prm->eta_max;
+    a.dr_min = prm->dr_min;
+    a.grid = grid;
+    a.grid_b = grid_b;
+    a.p = p;
+    a.w = w;
+    a.pass = pass;
+    a.bin_idx = bin_idx;
+    a.jac = jac;
+    a.x_out = x_out;
+    a.x12 = x12;
+    a.fail_count = h->fail_dev;
+    hipError_t e = mf::launch_phase_space_pp(a, mf::n_out(proc), static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "mf_phase_space_pp launch");
     return MF_OK;
 }
 
@@ -463,7 +552,7 @@ static mf_status vegas_args(const char* who, const mf_params* prm, int64_t n, in
                             double* edges, int flags, uint64_t* rng_counter, mf::VegasArgs& a)
 {
     if (!prm) return fail(MF_ERR_INVALID_ARG, "%s: NULL params", who);
-    if (d < 1 || d > 8) return fail(MF_ERR_INVALID_ARG, "%s: d = %d outside [1, 8]", who, d);
+    if (d < 1 || d > mf::VEGAS_MAX_D) return fail(MF_ERR_INVALID_ARG, "%s: d = %d outside [1, 16]", who, d);
     if (nb < 2 || nb > 64) return fail(MF_ERR_INVALID_ARG, "%s: nb = %d outside [2, 64]", who, nb);
     if (n < 0 || n > kMaxEvents) return fail(MF_ERR_INVALID_ARG, "%s: n outside [0, 2^36]", who);
     if (!acc || !edges) return fail(MF_ERR_INVALID_ARG, "%s: NULL acc or edges", who);

@@ -71,31 +71,7 @@ __global__ __launch_bounds__(256) void k_phase_space(PsArgs a)
     const bool ok = rambo_event<NOUT, double>(y, rs, a.m_out, P, &wgt);
     if (!ok && a.fail_count) atomicAdd(a.fail_count, 1ull);
     // ---- cuts on the final gluons (outgoing index >= 2 for the gg processes)
-    bool pass = true;
-    if (a.pass) {
-        double eta_[2] = {0.0, 0.0}, phi_[2] = {0.0, 0.0};
-        int ng = 0;
-#pragma unroll
-        for (int i = 2; i < NOUT; ++i) {
-            const double pt = sqrt(P[i][1] * P[i][1] + P[i][2] * P[i][2]);
-            const double pa = sqrt(pt * pt + P[i][3] * P[i][3]);
-            const double eta = atanh(P[i][3] / pa);
-            pass = pass && (pt > a.pt_min) && (fabs(eta) < a.eta_max);
-            eta_[ng] = eta;
-            phi_[ng] = atan2(P[i][2], P[i][1]);
-            ++ng;
-        }
-        if (ng == 2) {
-            double dphi = phi_[0] - phi_[1];
-            // wrap into [-pi, pi): same convention as remainder(x + pi, 2 pi) - pi
-            dphi = dphi + 3.141592653589793238463;
-            dphi = dphi - kTwoPiPs * floor(dphi / kTwoPiPs);
-            dphi = dphi - 3.141592653589793238463;
-            const double deta = eta_[0] - eta_[1];
-            pass = pass && (sqrt(deta * deta + dphi * dphi) > a.dr_min);
-        }
-        a.pass[e] = pass ? 1 : 0;
-    }
+    if (a.pass) a.pass[e] = gluon_cuts<NOUT>(P, 0.0, a.pt_min, a.eta_max, a.dr_min) ? 1 : 0;
     // ---- outputs: incoming legs then outgoing, [leg][comp][event]
     const double E = 0.5 * rs;
     const double inc[2][4] = {{E, 0.0, 0.0, E}, {E, 0.0, 0.0, -E}};
@@ -122,6 +98,7 @@ hipError_t launch_phase_space(const PsArgs& a, hipStream_t s)
     case 2: hipLaunchKernelGGL(k_phase_space<2>, dim3(grid), dim3(block), 0, s, a); break;
     case 3: hipLaunchKernelGGL(k_phase_space<3>, dim3(grid), dim3(block), 0, s, a); break;
     case 4: hipLaunchKernelGGL(k_phase_space<4>, dim3(grid), dim3(block), 0, s, a); break;
+    case 5: hipLaunchKernelGGL(k_phase_space<5>, dim3(grid), dim3(block), 0, s, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

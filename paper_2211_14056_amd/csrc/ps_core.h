@@ -162,7 +162,9 @@ __device__ __forceinline__ bool rambo_event(const KT* y, double rs, const KT* m,
     double lo = 0.0, hi = 1.0;
     double xi = sqrt(fmax(1.0 - (msum / rs) * (msum / rs), 0.0));
     bool ok = false;
-    for (int it = 0; it < 50; ++it) {
+    // F(0) = sum m - sqrt(s) < 0 <= F(1) brackets the root; at or below threshold there is
+    // none and the event fails
+    for (int it = 0; msum < rs && it < 50; ++it) {
         double F = -rs, dF = 0.0;
 #pragma unroll
         for (int i = 0; i < NOUT; ++i) {
@@ -171,8 +173,12 @@ __device__ __forceinline__ bool rambo_event(const KT* y, double rs, const KT* m,
             F += r;
             dF += xi * E * E / r;
         }
-        if (F == 0.0) { ok = true; break; }     // exact root
+        // converged when the residual is at the rounding level of its own evaluation (NOUT
+        // square roots of size up to sqrt(s)): near threshold (xi -> 0) F'(xi) -> 0, so the
+        // Newton step there is rounding noise and a step-size test alone would never pass
+        if (fabs(F) <= 4.5e-16 * NOUT * rs) { ok = true; break; }
         if (F > 0.0) hi = xi; else lo = xi;
+        if (hi - lo <= 4.5e-16 * hi) { ok = true; break; }     // bracket at the last bits
         double nx = xi - F / dF;
         if (!(nx >= lo && nx <= hi)) nx = 0.5 * (lo + hi);
         const double dx = fabs(nx - xi);
@@ -188,7 +194,7 @@ __device__ __forceinline__ bool rambo_event(const KT* y, double rs, const KT* m,
         F = F + r;
         dF += xi * kval(P[i][0]) * kval(P[i][0]) / kval(r);
     }
-    const KT xik = KT(xi) - F / dF;
+    const KT xik = dF > 0.0 ? KT(xi) - F / dF : KT(xi);
     double sk = 0.0, pk = 1.0, s2 = 0.0;
 #pragma unroll
     for (int i = 0; i < NOUT; ++i) {
@@ -213,6 +219,39 @@ __device__ __forceinline__ bool rambo_event(const KT* y, double rs, const KT* m,
         if (!ok) *wgt = 0.0;
     }
     return ok;
+}
+
+// Generation cuts on the final gluons (outgoing particles 2 .. NOUT-1; the tops are not
+// cut): pT > pt_min and |eta + y| < eta_max for each, Delta R > dr_min for every pair, with
+// eta = atanh(pz/|p|) and Delta phi wrapped into [-pi, pi).  y shifts the pseudorapidities
+// (a longitudinal boost of massless particles; 0 in the c.m. frame).  Strict inequalities.
+template <int NOUT>
+__device__ __forceinline__ bool gluon_cuts(const double (&P)[NOUT][4], double y, double pt_min, double eta_max,
+                                           double dr_min)
+{
+    constexpr int NG = NOUT > 2 ? NOUT - 2 : 1;
+    double eta_[NG], phi_[NG];
+    bool pass = true;
+#pragma unroll
+    for (int i = 2; i < NOUT; ++i) {
+        const double pt = sqrt(P[i][1] * P[i][1] + P[i][2] * P[i][2]);
+        const double pa = sqrt(pt * pt + P[i][3] * P[i][3]);
+        const double eta = atanh(P[i][3] / pa) + y;
+        pass = pass && (pt > pt_min) && (fabs(eta) < eta_max);
+        eta_[i - 2] = eta;
+        phi_[i - 2] = atan2(P[i][2], P[i][1]);
+    }
+#pragma unroll
+    for (int i = 0; i + 2 < NOUT; ++i)
+#pragma unroll
+        for (int j = i + 1; j + 2 < NOUT; ++j) {
+            // wrap into [-pi, pi): the convention of remainder(x + pi, 2 pi) - pi
+            double dphi = phi_[i] - phi_[j] + 3.141592653589793238463;
+            dphi = dphi - kTwoPiPs * floor(dphi / kTwoPiPs) - 3.141592653589793238463;
+            const double deta = eta_[i] - eta_[j];
+            pass = pass && (sqrt(deta * deta + dphi * dphi) > dr_min);
+        }
+    return pass;
 }
 
 }  // namespace mf

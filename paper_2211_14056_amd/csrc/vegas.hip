@@ -14,8 +14,8 @@
 //  * block partials (sum F, sum F^2, histogram) go to a cell-major workspace,
 //    and one workgroup sums them (a wave per cell, fixed lane order and a
 //    fixed butterfly) and then refines the grid.
-// F = flux * w * J_vegas * ME for events that pass the cuts and have w > 0
-// (0 otherwise) is formed here from the phase-space weight, the Vegas Jacobian
+// F = flux * w * J_vegas * ME for events that pass the cuts and have a weight
+// that is neither 0 nor NaN (0 otherwise) is formed here from the phase-space weight, the Vegas Jacobian
 // and the matrix element, so it never round-trips through memory unless the
 // caller asks for it.
 #include <mutex>
@@ -27,19 +27,22 @@ namespace {
 
 constexpr int VB = 256;           // threads per block
 constexpr int WAVES = VB / 64;
-constexpr int MAXD = 8;
+constexpr int MAXD = VEGAS_MAX_D;
 constexpr int MAXNB = 64;
 static_assert(2 + MAXD * MAXNB == VEGAS_MAX_CELLS, "workspace size");
 
+// MD: histogram rows held in LDS (8 serves the partonic processes up to four final-state
+// particles with a small footprint; 16 the hadronic and larger ones)
+template <int MD>
 __global__ __launch_bounds__(VB) void k_vegas_accumulate(VegasArgs a)
 {
-    __shared__ double hist[WAVES][MAXD][MAXNB];
+    __shared__ double hist[WAVES][MD][MAXNB];
     __shared__ double fsq[WAVES][64];
-    __shared__ short bins[WAVES][MAXD][64];
+    __shared__ short bins[WAVES][MD][64];
     __shared__ double red[2][VB];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int d = a.d, nb = a.nb;
-    for (int c = lane; c < MAXD * MAXNB; c += 64) hist[wv][c / MAXNB][c % MAXNB] = 0.0;
+    for (int c = lane; c < MD * MAXNB; c += 64) hist[wv][c / MAXNB][c % MAXNB] = 0.0;
     double sf = 0.0, sf2 = 0.0;
     const int64_t n = a.n;
     for (int64_t chunk = blockIdx.x; chunk * VB < n; chunk += gridDim.x) {
@@ -51,9 +54,10 @@ __global__ __launch_bounds__(VB) void k_vegas_accumulate(VegasArgs a)
             const bool ps = a.pass ? a.pass[e] != 0 : true;
             const double jac = a.jac ? a.jac[e] : 1.0;
             const double w = a.w[e];
-            // an event outside the cuts or without weight (a failed phase-space
-            // solve, NaN uniforms) contributes exactly 0, whatever its |M|^2 holds
-            F = (ps && w > 0.0) ? a.flux * w * jac * me : 0.0;
+            // an event outside the cuts or without weight (a failed phase-space solve
+            // gives 0, NaN uniforms NaN) contributes exactly 0, whatever its |M|^2 holds;
+            // a negative weight (a parton density below zero) counts as it is
+            F = (ps && w == w && w != 0.0) ? a.flux * w * jac * me : 0.0;
             if (a.F) a.F[e] = F;
         }
         sf += F;
@@ -168,7 +172,7 @@ __global__ __launch_bounds__(64) void k_vegas_update(VegasArgs a)
 }  // namespace
 
 // Block partials of mf_vegas_refine_noalloc: a library-owned array of the largest size
-// any call needs (VEGAS_PARTIALS_MAX doubles, 4.2 MB), one copy per device, held until
+// any call needs (VEGAS_PARTIALS_MAX doubles, 8.4 MB), one copy per device, held until
 // the process ends.  Every call writes all the cells it reads, so nothing needs clearing.
 // In host code `scratch` only names the symbol; kernels get the device address found by
 // vegas_static_partials.
@@ -208,7 +212,8 @@ hipError_t launch_vegas(const VegasArgs& a, hipStream_t s)
 {
     if (a.d > MAXD || a.nb > MAXNB || a.nb < 2) return hipErrorInvalidValue;
     // n = 0 still runs the accumulation: every block then writes zero partials
-    hipLaunchKernelGGL(k_vegas_accumulate, dim3(a.nblk), dim3(VB), 0, s, a);
+    if (a.d <= 8) hipLaunchKernelGGL(k_vegas_accumulate<8>, dim3(a.nblk), dim3(VB), 0, s, a);
+    else hipLaunchKernelGGL(k_vegas_accumulate<MAXD>, dim3(a.nblk), dim3(VB), 0, s, a);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
     hipLaunchKernelGGL(k_vegas_reduce, dim3(2 + a.d * a.nb), dim3(64), 0, s, a);

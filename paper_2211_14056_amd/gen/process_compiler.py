@@ -757,7 +757,71 @@ def _adj_lvalue(n):
     return n[:i] + '_b' + n[i:]
 
 
-def emit_qcd_adjoint(proc, opaque_inputs=True, group_barriers=True):
+def _regrouped_quark_sweeps(proc, ir, g_read, ext_adj, group_barriers):
+    """Reverse sweep of the quark line by groups of orderings with the same first gluon.
+
+    The forward quark line and colour sums have run; the colour sums' sweep gives the
+    adjoints of the amplitudes.  Per group, the statements its amplitudes depend on are
+    emitted again under new names (recomputation) and swept backwards from those adjoints,
+    so only one group's quark-line values are live during a sweep.  Returns (lines, flops
+    of the recomputation, flops of the sweeps)."""
+    import re as _re
+    from .adjoint import Adjoint, base_sign
+    q = ir.q
+    ops = {name: (kind, name, operands) for kind, name, operands in q.ops}
+    order = [name for _, name, _ in q.ops]
+    text = {}
+    for l in q.lines:
+        m = _re.match(r'const R (u\d+) = ', l)
+        if m:
+            text[m.group(1)] = l
+    flops_of = {}
+    for l in q.lines:
+        m = _re.match(r'const R (u\d+) = (.*);', l)
+        if m:
+            e = m.group(2)
+            flops_of[m.group(1)] = 2 if e.startswith('fma(') else (1 if (' + ' in e or ' * ' in e) else 0)
+    lines, rec_flops, sweep_flops = [], 0, 0
+    for g in range(proc.k):
+        outs = [ir.amps[h][si] for h in range(2) for si, sig in enumerate(proc.orderings) if sig[0] == g]
+        need = set()
+        stack = [base_sign(x)[0] for a in outs for x in (a.re, a.im) if not x.is_const]
+        while stack:
+            n = stack.pop()
+            if n in need or n not in ops:
+                continue
+            need.add(n)
+            for x in ops[n][2]:
+                if not x.is_const:
+                    stack.append(base_sign(x)[0])
+        pfx = f'q{g}_'
+        ren = lambda n: pfx + n if n in need else n          # noqa: E731
+
+        def rn(x):
+            if x.is_const:
+                return x
+            b, sgn = base_sign(x)
+            return S(name=ren(b) if sgn > 0 else f'(-{ren(b)})')
+        sub = [n for n in order if n in need]
+        if group_barriers:
+            lines.append('__builtin_amdgcn_sched_barrier(0);')
+        for n in sub:
+            lines.append(_re.sub(r'\bu(\d+)\b', lambda m: ren('u' + m.group(1)), text[n]))
+            rec_flops += flops_of.get(n, 0)
+        a = Adjoint({ren(n) for n in sub} | set(g_read), ext_adj, declared=g_read)
+        for amp in outs:
+            for x in (amp.re, amp.im):
+                if not x.is_const:
+                    b, sgn = base_sign(x)
+                    a.seed(S(name=ren(b)), f'{b}_b' if sgn > 0 else f'(-{b}_b)')
+        a.sweep([(kind, ren(name), tuple(rn(x) for x in operands)) for kind, name, operands in
+                 (ops[n] for n in sub)])
+        lines += a.lines
+        sweep_flops += a.flops
+    return lines, rec_flops, sweep_flops
+
+
+def emit_qcd_adjoint(proc, opaque_inputs=True, group_barriers=True, regroup=False):
     """Adjoint (reverse sweep) of the helicity-summed, colour-contracted |M|^2 with respect
     to the kinematic inputs z (emit_kin), recomputing every current per helicity.
 
@@ -767,7 +831,7 @@ def emit_qcd_adjoint(proc, opaque_inputs=True, group_barriers=True):
     top-helicity loop the gluon currents are recomputed (no value of the first pass is
     kept across the loop except the currents the quark line reads) and swept backwards.
     Nothing is stored in memory.  Returns (source, flop counts)."""
-    from .adjoint import Adjoint, operand_names, defined_names
+    from .adjoint import Adjoint, base_sign, operand_names, defined_names
     k = proc.k
     ir = _build_ir(proc, 0, False, False, group_barriers)
     b, q, cs = ir.b, ir.q, ir.cs
@@ -831,13 +895,28 @@ def emit_qcd_adjoint(proc, opaque_inputs=True, group_barriers=True):
     body += ['        ' + l for l in q.lines]
     body += ['        ' + l for l in cs.lines]
     body.append(f'        me += {cs.ref(ir.csq[0])} + {cs.ref(ir.csq[1])};')
-    aq = Adjoint(set(qc_temps) | set(g_read), _adj_lvalue, declared=g_read)
-    for h in range(2):
-        aq.seed(ir.csq[h], 'R(1)')
-    aq.sweep(qc_ops)
-    if group_barriers:
-        body.append('        __builtin_amdgcn_sched_barrier(0);')
-    body += ['        ' + l for l in aq.lines]
+    rec_q = 0
+    if regroup:
+        # colour sums backwards to the amplitudes, then the quark line group by group
+        amp_names = {base_sign(x)[0] for row in ir.amps for a in row for x in (a.re, a.im) if not x.is_const}
+        aq = Adjoint(set(defined_names(cs.ops)) | amp_names, _adj_lvalue)
+        for h in range(2):
+            aq.seed(ir.csq[h], 'R(1)')
+        aq.sweep(cs.ops)
+        if group_barriers:
+            body.append('        __builtin_amdgcn_sched_barrier(0);')
+        body += ['        ' + l for l in aq.lines]
+        glines, rec_q, sw = _regrouped_quark_sweeps(proc, ir, g_read, _adj_lvalue, group_barriers)
+        body += ['        ' + l for l in glines]
+        aq.flops += sw
+    else:
+        aq = Adjoint(set(qc_temps) | set(g_read), _adj_lvalue, declared=g_read)
+        for h in range(2):
+            aq.seed(ir.csq[h], 'R(1)')
+        aq.sweep(qc_ops)
+        if group_barriers:
+            body.append('        __builtin_amdgcn_sched_barrier(0);')
+        body += ['        ' + l for l in aq.lines]
     body.append('        for (int j = 0; j < 4; ++j) {')
     body.append('            cplx<R>& t = ht ? ub_b[1][j] : ub_b[0][j];')
     body.append('            t.re += ubs_b[j].re;')
@@ -862,7 +941,7 @@ def emit_qcd_adjoint(proc, opaque_inputs=True, group_barriers=True):
             body.append(f'zb[{i}] = {_adj_lvalue(n)};')
     out += ['    ' + l for l in body]
     out.append('}')
-    per_gconf = 2 * ir.gluon_flops + ag.flops + 2 * (ir.quark_flops + ir.colour_flops + 1 + aq.flops)
+    per_gconf = 2 * ir.gluon_flops + ag.flops + 2 * (ir.quark_flops + rec_q + ir.colour_flops + 1 + aq.flops)
     flops = dict(adjoint_per_event=(2 ** (k - 1)) * per_gconf, kin_slots=len(slots),
                  adjoint_gluon_sweep=ag.flops, adjoint_quark_colour_sweep=aq.flops)
     out.append(f'// flops per event of the adjoint (generated count): {flops}')
@@ -979,6 +1058,23 @@ def emit_all(outdir, **opts):
             f.write(src_adj + '\n')
         flops.update(info_adj)
         summary[name] = flops
+    # gg -> ttbar ggg: tables of the table-driven recursion (one wavefront per event)
+    from . import bg_tables
+    src_bg, _ = bg_tables.emit(5, 'bg5')
+    with open(os.path.join(outdir, 'me_bg_k5.inc'), 'w') as f:
+        f.write('// Generated by paper_2211_14056_amd.gen.bg_tables -- do not edit.\n')
+        f.write(src_bg)
+    summary['gg_ttggg'] = bg_tables.flops(5)
+    # the processes with two quark lines: generated diagram code (one lane per event)
+    from . import quark_lines
+    for qp in quark_lines.PROCESSES:
+        src_q, info_q = quark_lines.emit(qp)
+        with open(os.path.join(outdir, f'me_{qp}.inc'), 'w') as f:
+            f.write('// Generated by paper_2211_14056_amd.gen.quark_lines -- do not edit.\n')
+            f.write(src_q)
+        info_q.update(per_event_f64=info_q['per_event'], per_event_f32=info_q['per_event'],
+                      per_event_f32_valu=info_q['per_event'])
+        summary[qp] = info_q
     with open(os.path.join(outdir, 'flops.txt'), 'w') as f:
         for name, fl in summary.items():
             f.write(f'{name} {fl}\n')

@@ -35,9 +35,9 @@ def test_library_exports_every_declared_symbol():
 @pytest.mark.skipif(not os.path.exists(LIB), reason='library not built')
 def test_host_only_helpers():
     L = ctypes.CDLL(LIB)
-    assert [L.mf_process_legs(i) for i in range(4)] == [4, 4, 5, 6]
-    assert [L.mf_process_dims(i) for i in range(4)] == [2, 2, 5, 8]
-    assert L.mf_process_legs(7) == -1
+    assert [L.mf_process_legs(i) for i in range(10)] == [4, 4, 5, 6, 7, 4, 5, 6, 5, 6]
+    assert [L.mf_process_dims(i) for i in range(10)] == [2, 2, 5, 8, 11, 2, 5, 8, 5, 8]
+    assert L.mf_process_legs(10) == -1 and L.mf_process_dims(-1) == -1
     L.mf_last_error.restype = ctypes.c_char_p
     # argument validation happens before any device work
     L.mf_create.argtypes = [ctypes.c_int, ctypes.c_void_p]
@@ -51,13 +51,24 @@ def test_binding_has_same_names_as_header():
         assert callable(getattr(mf, n))
 
 
+def test_binding_process_ids_match_header():
+    import paper_2211_14056_amd as mf
+    text = open(os.path.join(ROOT, 'include', 'mf.h')).read()
+    body = re.search(r'typedef enum \{([^}]*)\} mf_process;', text).group(1)
+    ids = {k: int(v) for k, v in re.findall(r'(MF_[A-Z_]+) = (\d+)', body)}
+    assert len(ids) == 10
+    for name, v in ids.items():
+        assert getattr(mf, name) == v, name
+        assert mf.PROCESS[name[3:].lower()] == v
+
+
 def test_generated_colour_matrices_match_oracle_brute_force():
     import numpy as np
     from oracle import colour
     from paper_2211_14056_amd.gen import colour_algebra
-    for k in (2, 3, 4):
+    for k in (2, 3, 4, 5):
         num, den = colour_algebra.integer_form(colour_algebra.colour_matrix(k))
-        assert np.abs(np.array(num) / den - colour.colour_matrix(k)).max() < 1e-14
+        assert np.abs(np.array(num) / den - colour.colour_matrix(k)).max() < 1e-13
 
 
 def test_process_compiler_flop_counts_are_stable():
@@ -86,7 +97,7 @@ def test_noalloc_vegas_validates_arguments_before_any_device_work():
     import paper_2211_14056_amd as mf
     L = mf.lib()
     prm = mf.params()
-    for n, d, nb in ((10, 9, 50), (10, 2, 65), (10, 2, 1), (-1, 2, 50)):
+    for n, d, nb in ((10, 17, 50), (10, 2, 65), (10, 2, 1), (-1, 2, 50)):
         st = L.mf_vegas_refine_noalloc(ctypes.byref(prm), n, d, nb, 1.5, None, None, None, 0, None, None, None,
                                        None, None, 0, None, None)
         assert st == -1, (n, d, nb)

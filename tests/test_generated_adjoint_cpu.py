@@ -97,24 +97,28 @@ def _norms(proc):
 
 
 CASES = [
-    # (process, working type, tangent directions per kinematic pass, events)
-    ('gg_tt', 'double', 3, 16),
-    ('gg_ttg', 'double', 6, 16),
-    ('gg_ttg', 'double', 2, 6),
-    ('gg_ttg', 'float', 6, 16),
-    ('gg_ttgg', 'double', 3, 3),
-    ('gg_ttgg', 'float', 9, 3),
+    # (process, working type, tangent directions per kinematic pass, events, quark line swept by groups)
+    ('gg_tt', 'double', 3, 16, False),
+    ('gg_ttg', 'double', 6, 16, False),
+    ('gg_ttg', 'double', 2, 6, False),
+    ('gg_ttg', 'float', 6, 16, False),
+    ('gg_ttgg', 'double', 3, 3, False),
+    ('gg_ttgg', 'float', 9, 3, False),
+    ('gg_tt', 'double', 3, 8, True),
+    ('gg_ttg', 'double', 3, 16, True),
+    ('gg_ttg', 'float', 3, 16, True),
+    ('gg_ttgg', 'double', 3, 3, True),
 ]
 
 
 @pytest.mark.skipif(shutil.which('g++') is None, reason='needs a host C++ compiler')
-@pytest.mark.parametrize('proc,rtype,ch,n', CASES)
-def test_generated_adjoint_on_cpu_matches_oracle_gradient(tmp_path, proc, rtype, ch, n):
+@pytest.mark.parametrize('proc,rtype,ch,n,regroup', CASES)
+def test_generated_adjoint_on_cpu_matches_oracle_gradient(tmp_path, proc, rtype, ch, n, regroup):
     d_ = str(tmp_path)
     _host_headers(d_)
     legs = processes.PROCESSES[proc]['n_ext']
     gp = pc.GGTTProcess(proc, legs)
-    body, _ = pc.emit_qcd_adjoint(gp)
+    body, _ = pc.emit_qcd_adjoint(gp, regroup=regroup)
     open(os.path.join(d_, 'body.inc'), 'w').write(body + '\n')
     open(os.path.join(d_, 'driver.cpp'), 'w').write(DRIVER)
     exe = os.path.join(d_, 'vjp')
