@@ -161,6 +161,14 @@ mf_status mf_set_launch(mf_handle h, int proc, int precision, int block, int bat
  * (synchronises the handle's device). */
 mf_status mf_failures(mf_handle h, uint64_t* count);
 
+/* Tile of the persistent mixed-batch launch (mf_matrix_element with several requests;
+ * the paper's study of launch shapes, sect. 3, Fig. 3): each pop of the work queue takes
+ * `waves` 64-event waves of one request.  For MF_GG_TT and MF_GG_TTG only (gg -> t tbar g g
+ * takes one wave per tile); waves in [1, 64], 0 restores the default (16 for MF_GG_TT, 4
+ * for MF_GG_TTG).  Results do not depend on it.  Errors: MF_ERR_INVALID_ARG for another
+ * process or waves outside [0, 64]. */
+mf_status mf_set_batch_tile(mf_handle h, int proc, int waves);
+
 /*
  * mf_phase_space -- the sampling steps of the path (sect. 1; sect. 3 for the
  * cuts): uniforms, Vegas map, RAMBO-on-diet phase space with massive

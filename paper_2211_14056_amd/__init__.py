@@ -71,6 +71,8 @@ def lib():
     L.mf_precision_available.argtypes = [I32]
     L.mf_set_launch.argtypes = [VP, I32, I32, I32, I32, I32]
     L.mf_set_launch.restype = I32
+    L.mf_set_batch_tile.argtypes = [VP, I32, I32]
+    L.mf_set_batch_tile.restype = I32
     L.mf_phase_space.argtypes = [VP, I32, ctypes.POINTER(mf_params), I64, VP, U64, U64, VP, VP, I32,
                                  VP, VP, VP, VP, VP, VP, VP]
     L.mf_matrix_element.argtypes = [VP, ctypes.POINTER(mf_request), I32, I32, ctypes.POINTER(mf_params), VP]
@@ -174,6 +176,10 @@ class Handle:
     def set_launch(self, proc=-1, precision=0, block=0, batch_waves_per_cu=-1, batch_persistent=-1):
         """mf_set_launch: per-(process, precision) block size and persistent-batch grid."""
         _check(lib().mf_set_launch(self.h, proc, precision, block, batch_waves_per_cu, batch_persistent))
+
+    def set_batch_tile(self, proc, waves=0):
+        """mf_set_batch_tile: 64-event waves per tile of the persistent batch (0 = default)."""
+        _check(lib().mf_set_batch_tile(self.h, proc, waves))
 
     def failures(self):
         c = ctypes.c_uint64()

@@ -4,18 +4,23 @@ The paper shows that the block size chosen for its custom kernels changes
 the time of a fixed workload a lot, with a plateau of good choices (sect. 3,
 Fig. 3).  Here the same question is answered by measurement on the device at
 hand: for each (process, precision) the single-request matrix-element launch
-is timed for every candidate block size, and the persistent mixed-batch
-launches for every candidate grid (one-wave workgroups per compute unit, 0 =
-as many as fit) against one launch per request; the
-fastest is installed in the handle (mf_set_launch) and cached in a JSON file
-keyed by (GPU architecture, process, precision, batch-size bucket).
+is timed for every candidate launch shape (block size; for gg -> ttbar gg in
+FP64 the event layout, one, two or four lanes per event; for gg -> ttbar ggg
+the lanes per event of its one-wavefront-per-event kernel, 16, 32 or 64); the
+persistent mixed-batch launch for every candidate grid (one-wave workgroups per
+compute unit, 0 = as many as fit) against one launch per request, and for every
+candidate tile (64-event waves per work-queue pop, gg -> ttbar and gg -> ttbar g).
+The fastest is installed in the handle (mf_set_launch, mf_set_batch_tile) and
+cached in a JSON file keyed by (GPU architecture, process, precision, batch-size
+bucket).
 
 Environment: MF_TUNE = off | use | search (default use: apply cached entries,
 tune nothing); MF_TUNE_CACHE = path of the cache (default
 ~/.cache/mfhip/tuning.json).
 
 `python -m paper_2211_14056_amd.autotune --report` prints the measured curves
-(events/s against block size, event layout and persistent grid) as markdown.
+(events/s against block size, event layout, lanes per event, persistent grid and
+tile) as markdown.
 """
 import json
 import math
@@ -28,6 +33,18 @@ from . import (MF_FP64, PRECISION, PROCESS, make_request, mf_matrix_element, mf_
 
 BLOCKS = (64, 128, 192, 256)
 WAVES_PER_CU = (0, 1, 2, 4)     # 0 = as many as fit
+LANES_PER_EVENT = (16, 32, 64)  # gg -> ttbar ggg
+TILES = {'gg_tt': (4, 16, 64), 'gg_ttg': (1, 4, 16)}   # 64-event waves per tile of the persistent batch
+TTGG_LAYOUTS = (64, 128, 256)   # gg -> ttbar gg in FP64: one, two, four lanes per event
+
+
+def candidates(proc, precision):
+    """Launch shapes mf_set_launch accepts for (process, precision)."""
+    if proc == 'gg_ttggg':
+        return LANES_PER_EVENT
+    if proc == 'gg_ttgg' and precision == MF_FP64:
+        return TTGG_LAYOUTS
+    return BLOCKS
 
 
 def cache_path():
@@ -75,10 +92,13 @@ def _time(fn, reps=3):
     return best
 
 
-def sweep_block(h, proc, precision, n, prm=None, blocks=BLOCKS):
-    """Time of one launch over n events for each block size: {block: ms}."""
+def sweep_block(h, proc, precision, n, prm=None, blocks=None):
+    """Time of one launch over n events for each launch shape: {block: ms}."""
     prm = prm or params()
     pid = PROCESS[proc] if isinstance(proc, str) else proc
+    if blocks is None:
+        name = proc if isinstance(proc, str) else [k for k, v in PROCESS.items() if v == proc][0]
+        blocks = candidates(name, precision)
     p = _events(h, pid, n, prm)
     out = torch.empty(n, dtype=torch.float64 if precision == MF_FP64 else torch.float32, device=p.device)
     req = [make_request(pid, p, out)]
@@ -86,6 +106,7 @@ def sweep_block(h, proc, precision, n, prm=None, blocks=BLOCKS):
     for blk in blocks:
         h.set_launch(pid, precision, blk)
         res[blk] = _time(lambda: mf_matrix_element(h, req, precision, prm))
+    h.set_launch(pid, precision, 0)
     return res
 
 
@@ -105,6 +126,26 @@ def sweep_batch(h, requests, precision, prm=None, waves=WAVES_PER_CU):
     h.set_launch(batch_persistent=0)
     res['per_request'] = _time(lambda: mf_matrix_element(h, reqs, precision, prm))
     h.set_launch(batch_persistent=1)
+    return res
+
+
+def sweep_tile(h, requests, precision, proc, prm=None, tiles=None):
+    """Time of one persistent launch over `requests` for each tile size of process `proc`
+    (64-event waves per queue pop), the other processes at their defaults."""
+    prm = prm or params()
+    pid = PROCESS[proc]
+    reqs = []
+    for i, (pr, n) in enumerate(requests):
+        q = PROCESS[pr] if isinstance(pr, str) else pr
+        p = _events(h, q, n, prm, seed=100 + i)
+        out = torch.empty(n, dtype=torch.float64 if precision == MF_FP64 else torch.float32, device=p.device)
+        reqs.append(make_request(q, p, out))
+    h.set_launch(batch_persistent=1)
+    res = {}
+    for t in tiles or TILES[proc]:
+        h.set_batch_tile(pid, t)
+        res[t] = _time(lambda: mf_matrix_element(h, reqs, precision, prm))
+    h.set_batch_tile(pid, 0)
     return res
 
 
@@ -138,6 +179,16 @@ def tune(h, procs=('gg_tt', 'gg_ttg'), precisions=(MF_FP64,), n=1 << 18, batch=N
                 else:
                     h.set_launch(batch_waves_per_cu=int(c.split('_')[1]), batch_persistent=1)
                 used[key] = c
+            for proc in TILES:
+                if not any(pr == proc for pr, _ in batch):
+                    continue
+                key = f'{arch()}|batch_tile|{proc}|{prec}|{bucket(sum(n for _, n in batch))}'
+                if key not in cache and mode == 'search':
+                    t = sweep_tile(h, batch, prec, proc)
+                    cache[key] = dict(tile=min(t, key=t.get), times_ms=t)
+                if key in cache:
+                    h.set_batch_tile(PROCESS[proc], int(cache[key]['tile']))
+                    used[key] = cache[key]['tile']
     if mode == 'search':
         _save(cache)
     return used
@@ -158,12 +209,30 @@ def report(h, sizes=(1 << 16, 1 << 20), precisions=('fp64', 'fp32', 'fp32_mfma_b
                              + f' | {best} |')
                 h.set_launch(PROCESS[proc], PRECISION[pname], 0)
     n = 1 << 20
-    t = sweep_block(h, 'gg_ttgg', MF_FP64, n, blocks=(64, 128, 256))
-    h.set_launch(PROCESS['gg_ttgg'], MF_FP64, 0)
+    t = sweep_block(h, 'gg_ttgg', MF_FP64, n)
     lines += ['', '## Event layout, gg -> ttbar gg in FP64 (events/s in millions)', '',
               '| events | one lane per event | two lanes per event (default) | four lanes per event |',
               '|---|---|---|---|',
               f'| {n} | {n / t[64] / 1e3:.1f} | {n / t[128] / 1e3:.1f} | {n / t[256] / 1e3:.1f} |']
+    n5 = min(max(sizes), 1 << 18)
+    lines += ['', '## Lanes per event, gg -> ttbar ggg (events/s in millions)', '',
+              '| precision | events | ' + ' | '.join(f'{k} lanes' for k in LANES_PER_EVENT) + ' | best |',
+              '|---|---|' + '---|' * len(LANES_PER_EVENT) + '---|']
+    for pname in ('fp64', 'fp32'):
+        t = sweep_block(h, 'gg_ttggg', PRECISION[pname], n5)
+        best = min(t, key=t.get)
+        lines.append(f'| {pname} | {n5} | ' + ' | '.join(f'{n5 / t[k] / 1e3:.2f}' for k in LANES_PER_EVENT)
+                     + f' | {best} |')
+    lines += ['', '## Block size, quark-initiated processes (events/s in millions)', '',
+              '| process | precision | events | ' + ' | '.join(f'block {b}' for b in BLOCKS) + ' | best |',
+              '|---|---|---|' + '---|' * len(BLOCKS) + '---|']
+    nq = max(sizes)
+    for proc in ('qq_ttg', 'qq_ttgg', 'qg_ttqg'):
+        for pname in ('fp64', 'fp32'):
+            t = sweep_block(h, proc, PRECISION[pname], nq)
+            best = min(t, key=t.get)
+            lines.append(f'| {proc} | {pname} | {nq} | ' + ' | '.join(f'{nq / t[b] / 1e3:.1f}' for b in BLOCKS)
+                         + f' | {best} |')
     from .workloads import mixed_batch
     spec = mixed_batch(64, seed=5)
     total = sum(k for _, k in spec)
@@ -175,6 +244,11 @@ def report(h, sizes=(1 << 16, 1 << 20), precisions=('fp64', 'fp32', 'fp32_mfma_b
             f"persistent, {k.split('_')[1]} one-wave blocks per CU" + (' (as many as fit)' if k.endswith('_0') else '')
         lines.append(f'| {label} | {v:.2f} | {total / v / 1e3:.0f} |')
     h.set_launch(batch_waves_per_cu=0, batch_persistent=1)
+    lines += ['', '## Tile of the persistent batch (same 64 requests, ms per call; other processes at their '
+              'default tile)', '', '| process | ' + ' | '.join('tile' for _ in range(3)) + ' |', '|---|---|---|---|']
+    for proc in TILES:
+        t = sweep_tile(h, spec, PRECISION['fp32_mfma_bf16'], proc)
+        lines.append(f'| {proc} | ' + ' | '.join(f'{k} waves: {v:.2f}' for k, v in t.items()) + ' |')
     return '\n'.join(lines)
 
 

@@ -84,12 +84,14 @@ struct BatchReq {
     int64_t n;
     const double* p;
     void* out;
-    int64_t tile_begin;     // first tile of this request (64 * batch_chunk(proc) events per tile)
+    int64_t tile_begin;     // first tile of this request (64 * chunk events per tile)
 };
 
-// 64-event waves per tile of the persistent launch: cheap processes take several
-// per queue pop, so the queue's atomic is not on the critical path
+// 64-event waves per tile of the persistent launch (the default; mf_set_batch_tile changes it
+// for gg -> ttbar and gg -> ttbar g): cheap processes take several per queue pop, so the
+// queue's atomic is not on the critical path
 constexpr int batch_chunk(int proc) { return proc == GG_TT ? 16 : proc == GG_TTG ? 4 : 1; }
+constexpr int BATCH_CHUNK_MAX = 64;
 
 struct BatchArgs {
     BatchReq req[MAX_BATCH];
@@ -98,6 +100,7 @@ struct BatchArgs {
     unsigned* counter;      // device tile counter (reset by the launch)
     double mt;
     double coupling[4];     // per process: alpha (e+e-) or (4 pi alpha_s)^k
+    int chunk[4];           // per process: 64-event waves per tile (gg -> ttbar gg: always 1)
 };
 
 // One persistent launch over requests of one gg process; precision as for

@@ -106,9 +106,9 @@ __global__ __launch_bounds__(64) void k_me_batch(BatchArgs a)
         int r = 0;
         while (r + 1 < a.nreq && a.req[r + 1].tile_begin <= tile) ++r;
         const BatchReq q = a.req[r];
-        constexpr int CHUNK = batch_chunk(PROC);
-        const int64_t base = (tile - q.tile_begin) * (64 * CHUNK);
-        for (int c = 0; c < CHUNK && base + 64 * c < q.n; ++c) {
+        const int chunk = PROC == GG_TTGG ? 1 : a.chunk[PROC];
+        const int64_t base = (tile - q.tile_begin) * (64 * chunk);
+        for (int c = 0; c < chunk && base + 64 * c < q.n; ++c) {
             const int64_t e0 = base + 64 * c + lane;
             const int64_t e = e0 < q.n ? e0 : q.n - 1;
             const double me =
@@ -134,9 +134,9 @@ __global__ __launch_bounds__(64) void k_me_batch_grid(BatchArgs a)
     int r = 0;
     while (r + 1 < a.nreq && a.req[r + 1].tile_begin <= tile) ++r;
     const BatchReq q = a.req[r];
-    constexpr int CHUNK = batch_chunk(PROC);
-    const int64_t base = (tile - q.tile_begin) * (64 * CHUNK);
-    for (int c = 0; c < CHUNK && base + 64 * c < q.n; ++c) {
+    const int chunk = PROC == GG_TTGG ? 1 : a.chunk[PROC];
+    const int64_t base = (tile - q.tile_begin) * (64 * chunk);
+    for (int c = 0; c < chunk && base + 64 * c < q.n; ++c) {
         const int64_t e0 = base + 64 * c + lane;
         const int64_t e = e0 < q.n ? e0 : q.n - 1;
         const double me = batch_event<R, MODE, PROC>(q, e, a.mt, smem + lane) * a.coupling[PROC] * batch_norm<PROC>();

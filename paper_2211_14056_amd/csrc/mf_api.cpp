@@ -47,6 +47,7 @@ struct mf_handle_s {
     int block[mf::NPROC][4];           // [process][precision] threads per block, 0 = default
     int batch_waves_per_cu = 0;        // persistent grid = waves_per_cu * n_cu one-wave blocks (0: as many as fit)
     int batch_persistent = 1;          // 0 = one launch per request instead
+    int batch_chunk[4] = {1, mf::batch_chunk(mf::GG_TT), mf::batch_chunk(mf::GG_TTG), 1};   // waves per tile
 };
 
 namespace {
@@ -156,6 +157,18 @@ mf_status mf_set_launch(mf_handle h, int proc, int precision, int block, int bat
     return MF_OK;
 }
 
+mf_status mf_set_batch_tile(mf_handle h, int proc, int waves)
+{
+    g_err.clear();
+    if (!h) return fail(MF_ERR_INVALID_ARG, "mf_set_batch_tile: NULL handle");
+    if (proc != MF_GG_TT && proc != MF_GG_TTG)
+        return fail(MF_ERR_INVALID_ARG, "mf_set_batch_tile: process %d has a fixed tile", proc);
+    if (waves < 0 || waves > mf::BATCH_CHUNK_MAX)
+        return fail(MF_ERR_INVALID_ARG, "mf_set_batch_tile: waves = %d outside [0, %d]", waves, mf::BATCH_CHUNK_MAX);
+    h->batch_chunk[proc] = waves ? waves : mf::batch_chunk(proc);
+    return MF_OK;
+}
+
 mf_status mf_failures(mf_handle h, uint64_t* count)
 {
     g_err.clear();
@@ -262,6 +275,7 @@ mf_status mf_matrix_element(mf_handle h, const mf_request* reqs, int n_reqs, int
             double c = 1.0;
             for (int k = 0; k < mf::n_gluons(p); ++k) c *= 4.0 * 3.141592653589793238463 * prm->alpha_s;
             a.coupling[p] = c;
+            a.chunk[p] = h->batch_chunk[p];
         }
         auto flush = [&]() -> mf_status {
             if (a.nreq == 0) return MF_OK;
@@ -285,7 +299,7 @@ mf_status mf_matrix_element(mf_handle h, const mf_request* reqs, int n_reqs, int
                 q.p = r.p;
                 q.out = r.me_out;
                 q.tile_begin = a.ntiles;
-                const int64_t tile = 64 * mf::batch_chunk(r.proc);
+                const int64_t tile = 64 * a.chunk[r.proc];
                 a.ntiles += (r.n + tile - 1) / tile;
                 batched[i] = true;
             }

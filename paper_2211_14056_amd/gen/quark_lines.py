@@ -179,6 +179,8 @@ def enumerate_diagrams(proc):
                 for g_ in by_set.get(GS, []):
                     if r.type == ROW and r.flav == 'light' and g_.type == GLUON:
                         diagrams.append((r, g_))
+    # diagrams that share a row sub-tree next to each other: its value is live for a shorter span
+    diagrams.sort(key=lambda rg: (rg[0].id, rg[1].id))
     return legs, nodes, diagrams
 
 

@@ -993,6 +993,22 @@ def test_persistent_batch_equals_separate_launches(h, prec):
     tol = 1e-13 if prec == 'fp64' else 1e-6
     for x, y in zip(a, outs):
         assert float(((x.double() - y.double()).abs() / y.double().abs()).max()) <= tol
+    # other tiles of the work queue: the same kernel on the same events, bit for bit
+    for t_tt, t_ttg in ((1, 1), (64, 16), (3, 5)):
+        h.set_batch_tile(mf.MF_GG_TT, t_tt)
+        h.set_batch_tile(mf.MF_GG_TTG, t_ttg)
+        for o in outs:
+            o.fill_(float('nan'))
+        mf.mf_matrix_element(h, reqs, P_, mf.params())
+        torch.cuda.synchronize()
+        for x, y in zip(a, outs):
+            assert torch.equal(x, y), (t_tt, t_ttg)
+    h.set_batch_tile(mf.MF_GG_TT, 0)
+    h.set_batch_tile(mf.MF_GG_TTG, 0)
+    with pytest.raises(mf.MFError):
+        h.set_batch_tile(mf.MF_GG_TTGG, 2)
+    with pytest.raises(mf.MFError):
+        h.set_batch_tile(mf.MF_GG_TT, 65)
 
 
 def test_mixed_batch_full_size_one_launch(h):
@@ -1090,9 +1106,11 @@ def test_autotune_report(h):
     ev = gpu_events(h, 'gg_ttgg', 300, seed=8)
     before = mf.matrix_element(h, mf.MF_GG_TTGG, ev['p'], mf.MF_FP64)
     text = autotune.report(h, sizes=(1 << 12,))
-    for head in ('## Block size', '## Event layout', '## Persistent mixed batch'):
+    for head in ('## Block size', '## Event layout', '## Lanes per event', '## Block size, quark-initiated',
+                 '## Persistent mixed batch', '## Tile of the persistent batch'):
         assert head in text
-    assert text.count('| gg_tt |') == 3 and text.count('| gg_ttg |') == 3
+    assert text.count('| gg_tt | fp') == 3 and text.count('| gg_ttg | fp') == 3
+    assert text.count('| qq_ttgg | fp') == 2 and text.count(' waves: ') == 6
     after = mf.matrix_element(h, mf.MF_GG_TTGG, ev['p'], mf.MF_FP64)
     torch.cuda.synchronize()
     assert torch.equal(before, after)
@@ -1106,7 +1124,8 @@ def test_autotuner(h, tmp_path, monkeypatch):
     assert set(t) == set(autotune.BLOCKS) and all(v > 0 for v in t.values())
     used = autotune.tune(h, procs=('gg_tt',), precisions=(mf.MF_FP32,), n=1 << 16,
                          batch=[('gg_tt', 3000), ('gg_ttg', 2000), ('gg_ttgg', 500)], mode='search')
-    assert len(used) == 2
+    # block of gg_tt, the persistent grid, and the tiles of gg_tt and gg_ttg
+    assert len(used) == 4 and sum('batch_tile' in k for k in used) == 2
     import json
     c = json.load(open(tmp_path / 'tune.json'))
     assert any('batch' in k for k in c)
@@ -1119,3 +1138,5 @@ def test_autotuner(h, tmp_path, monkeypatch):
     torch.cuda.synchronize()
     assert torch.equal(a, b)
     h.set_launch(batch_persistent=1, batch_waves_per_cu=4)
+    h.set_batch_tile(mf.MF_GG_TT, 0)
+    h.set_batch_tile(mf.MF_GG_TTG, 0)
