@@ -8,6 +8,9 @@ space reads it and the Vegas reduction advances it by the batch size, so a
 captured HIP graph of one iteration (captured by the library, mf_graph_begin /
 mf_graph_end) can be replayed iteration after iteration with no host work in
 between except reading the two accumulated sums.
+
+With `pdf` the events are hadronic (mf_phase_space_pp: one parton channel of pp at
+sqrt_S, parton 1 with density `grid`, parton 2 with `grid_b`), d + 2 dimensions.
 """
 import math
 
@@ -15,19 +18,31 @@ import numpy as np
 import torch
 
 from . import (Handle, MF_FP64, PROCESS, make_request, mf_graph_begin, mf_graph_end, mf_matrix_element,
-               mf_phase_space, mf_process_dims, mf_process_legs, mf_vegas_refine, params)
+               mf_phase_space, mf_phase_space_pp, mf_process_dims, mf_process_legs, mf_vegas_refine, params)
 
 
 class VegasIntegrator:
     def __init__(self, proc, precision=MF_FP64, n=1_000_000, batches=1, nb=50, alpha=1.5, seed=1, prm=None,
-                 handle=None):
+                 handle=None, pdf=None):
+        """pdf: None (partonic events at prm.sqrt_s) or dict(grid=PdfGrid, grid_b=PdfGrid or None,
+        sqrt_S=collider energy) for hadronic events of one parton channel."""
         self.pid = PROCESS[proc] if isinstance(proc, str) else proc
         self.precision = precision
         self.n, self.batches, self.nb, self.alpha, self.seed = n, batches, nb, alpha, seed
         self.prm = prm or params()
         self.h = handle or Handle()
+        self.pdf = pdf
+        # the Vegas step forms the flux from sqrt(s): the collider's for hadronic events
+        self.vprm = self.prm
+        if pdf is not None:
+            from . import mf_params
+            v = mf_params()
+            for f, _ in mf_params._fields_:
+                setattr(v, f, getattr(self.prm, f))
+            v.sqrt_s = float(pdf['sqrt_S'])
+            self.vprm = v
         dev = torch.device('cuda', self.h.device)
-        d = mf_process_dims(self.pid)
+        d = mf_process_dims(self.pid) + (2 if pdf is not None else 0)
         self.d = d
         f64 = dict(dtype=torch.float64, device=dev)
         self.p = torch.empty(mf_process_legs(self.pid), 4, n, **f64)
@@ -53,11 +68,17 @@ class VegasIntegrator:
     def enqueue_iteration(self):
         """Enqueue one Vegas iteration on the current stream (capturable)."""
         for b in range(self.batches):
-            mf_phase_space(self.h, self.pid, self.prm, self.n, seed=self.seed, offset=0, offset_dev=self.counter,
-                           edges=self.edges, nb=self.nb, p=self.p, w=self.w, pass_=self.pass_,
-                           bin_idx=self.bins, jac=self.jac)
+            if self.pdf is None:
+                mf_phase_space(self.h, self.pid, self.prm, self.n, seed=self.seed, offset=0,
+                               offset_dev=self.counter, edges=self.edges, nb=self.nb, p=self.p, w=self.w,
+                               pass_=self.pass_, bin_idx=self.bins, jac=self.jac)
+            else:
+                mf_phase_space_pp(self.h, self.pid, self.prm, self.pdf['sqrt_S'], self.pdf['grid'], self.n,
+                                  seed=self.seed, offset=0, offset_dev=self.counter, edges=self.edges, nb=self.nb,
+                                  p=self.p, w=self.w, pass_=self.pass_, bin_idx=self.bins, jac=self.jac,
+                                  grid_b=self.pdf.get('grid_b'))
             mf_matrix_element(self.h, self.req, self.precision, self.prm)
-            mf_vegas_refine(self.h, self.prm, self.n, self.d, self.nb, self.alpha, self.w, self.jac, self.me,
+            mf_vegas_refine(self.h, self.vprm, self.n, self.d, self.nb, self.alpha, self.w, self.jac, self.me,
                             self.pass_, self.bins, self.acc, self.edges, update_edges=(b == self.batches - 1),
                             accumulate=(b > 0), rng_counter=self.counter)
 

@@ -12,7 +12,9 @@ the matrix-core precisions and the derivative rejected before any launch; at 2^2
 against FP64 on every event that passes the cuts, and bitwise repeatability.  Hadronic events:
 q g -> t tbar q with the toy quark and gluon densities against the oracle per event, and the
 q qbar -> t tbar part of sigma(pp) from 4e6 GPU events within four Monte Carlo errors of the
-quadrature of f_q f_qbar times the closed-form partonic cross section.
+quadrature of f_q f_qbar times the closed-form partonic cross section; sigma(pp -> t tbar) summed
+over all its parton channels (gg, q qbar, qbar q) within four errors of the sum of the
+quadratures; every channel of pp -> t tbar + jet finite and positive.
 """
 import sys
 
@@ -264,3 +266,33 @@ def test_sigma_pp_qq_tt_matches_quadrature(h, grids):
     say('  sigma', I, '+-', sig, 'quadrature', ref)
     assert abs(I - ref) < 4 * sig
     assert sig / I < 2e-3
+
+
+def test_sigma_pp_tt_all_channels_matches_quadrature(h, grids):
+    """sigma(pp -> ttbar) summed over its parton channels (hadronic.sigma_pp: gg once, q qbar
+    twice for the beam-swapped qbar q) against the oracle's quadratures of the closed forms."""
+    from paper_2211_14056_amd import hadronic
+    ref = (opdf.sigma_pp_gg_tt_quadrature(grids['g'], SQRT_S ** 2, P)
+           + 2 * opdf.sigma_pp_qq_tt_quadrature(grids['q'], grids['qbar'], SQRT_S ** 2, P))
+    say('sigma pp -> ttbar, all channels')
+    r = hadronic.sigma_pp('tt', sqrt_S=SQRT_S, n=1_000_000, iters=3, warmup=1, prm=mf.params_from_dict(P),
+                          handle=h)
+    say('  sigma', r['sigma_pb'], '+-', r['error_pb'], 'quadrature', ref, r['channels'])
+    assert abs(r['sigma_pb'] - ref) < 4 * r['error_pb']
+    assert r['error_pb'] / r['sigma_pb'] < 2e-3
+
+
+def test_sigma_pp_tt_jet_channels(h):
+    """pp -> ttbar + jet (pT > 20 GeV, |eta| < 2.5): every tree-level channel of one light
+    flavour integrates to a finite positive cross section with a small error, and the total is
+    the multiplicity-weighted sum."""
+    from paper_2211_14056_amd import hadronic
+    say('sigma pp -> ttbar + jet')
+    r = hadronic.sigma_pp('ttj', sqrt_S=SQRT_S, n=1 << 18, iters=2, warmup=1, prm=mf.params_from_dict(P),
+                          handle=h)
+    say('  ', r)
+    ch = r['channels']
+    assert len(ch) == 4
+    for v in ch.values():
+        assert np.isfinite(v['sigma_pb']) and v['sigma_pb'] > 0 and v['error_pb'] < 0.05 * v['sigma_pb']
+    assert abs(sum(v['sigma_pb'] for v in ch.values()) - r['sigma_pb']) <= 1e-12 * r['sigma_pb']
