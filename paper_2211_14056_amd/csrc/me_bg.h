@@ -10,8 +10,8 @@
 // of the colour matrix.  The tables (gen/bg_tables.py) hold the splits; the vertex
 // forms, the quark line and the colour matrix are those of the straight-line code
 // (gen/process_compiler.py), so the same table kernel for 3 and 4 gluons reproduces the
-// straight-line kernels.  Currents, prefixes and amplitudes live in LDS (~15 KB per event
-// in FP32), kinematics are evaluated once per event in FP64 and rounded.
+// straight-line kernels.  Currents, prefixes and amplitudes live in LDS (11.7 KB per event
+// in FP32, 23 KB in FP64), kinematics are evaluated once per event in FP64 and rounded.
 #pragma once
 #include "internal.h"
 #include "me_common.h"
@@ -23,9 +23,10 @@ template <int K> struct BgTab;
 
 template <int K, typename R>
 struct BgShared {
-    static constexpr int NCUR = BgTab<K>::NCUR, NPRE = BgTab<K>::NPRE, NORD = BgTab<K>::NORD;
+    static constexpr int NCUR = BgTab<K>::NCUR, NPRE = BgTab<K>::NPRE_STORED, NORD = BgTab<K>::NORD;
     R J[NCUR][8];             // currents, light-cone components (+, -, t, tb) x (re, im)
-    R Q[NPRE][8];             // quark-line row spinors after the prefix, propagator included
+    R Q[NPRE][8];             // quark-line row spinors after the prefixes shorter than K - 1,
+                              // propagator included
     R A[2][NORD][2];          // amplitudes per antitop helicity
     R P[1 << K][4];           // gluon-subset momentum sums (incoming convention): E+z, E-z, x, y
     R ig[1 << K];             // 1 / P^2
@@ -227,9 +228,10 @@ __device__ double bg_event(const double (&pe)[K + 2][4], double mt, BgShared<K, 
         for (int ht = 0; ht < 2; ++ht) {
             for (int j = lane; j < 8; j += LPE) sh.Q[0][j] = sh.ub[ht][j];
             __syncthreads();
-            // ---- quark line: prefixes by length
+            // ---- quark line: prefixes by length, up to K - 2 (a prefix of length K - 1 fixes
+            // its ordering, whose lane forms it below without storing it)
 #pragma unroll 1
-            for (int L = 1; L < K; ++L) {
+            for (int L = 1; L < K - 1; ++L) {
                 for (int q = T::pre_levels(L) + lane; q < T::pre_levels(L + 1); q += LPE) {
                     V4c<R> psi{};
                     for (int s = 0; s < L; ++s) {
@@ -248,11 +250,26 @@ __device__ double bg_event(const double (&pe)[K + 2][4], double mt, BgShared<K, 
             }
             // ---- amplitudes of the orderings
             for (int o = lane; o < T::NORD; o += LPE) {
+                // the ordering's prefix of length K - 1 (all gluons but the last), in registers
+                const short* last = T::ord_split(o, K - 1);
+                const int q = last[0];
+                V4c<R> psi{};
+                for (int s = 0; s < K - 1; ++s) {
+                    const short* sp = T::pre_split(q, s);
+                    slash_row_add(load8(sh.Q[sp[0]], R(1)), load8(sh.J[sp[1]], sp[2] ? R(-1) : R(1)), psi);
+                }
+                const R* qp = sh.qp[T::pre_mask(q)];
+                const V4c<R> ql = V4c<R>{{{qp[0], R(0)}, {qp[1], R(0)}, {qp[2], qp[3]}, {qp[2], -qp[3]}}};
+                V4c<R> qlast;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) qlast.c[j] = cscale(psi.c[j], qp[4]);
+                slash_row_add(psi, ql, qlast);
                 V4c<R> full{};
-                for (int s = 0; s < K; ++s) {
+                for (int s = 0; s < K - 1; ++s) {
                     const short* sp = T::ord_split(o, s);
                     slash_row_add(load8(sh.Q[sp[0]], R(1)), load8(sh.J[sp[1]], sp[2] ? R(-1) : R(1)), full);
                 }
+                slash_row_add(qlast, load8(sh.J[last[1]], last[2] ? R(-1) : R(1)), full);
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
                     cx<R> a = {R(0), R(0)};

@@ -158,6 +158,9 @@ def emit(k, name):
           'template <int K> struct BgTab;',
           f'template <> struct BgTab<{k}> {{',
           f'    static constexpr int NCUR = {len(cu)}, NPRE = {len(pr)}, NORD = {len(od)}, CDEN = {t["cden"]};',
+          f'    // prefixes shorter than k - 1 (the ones kept in LDS; each prefix of length k - 1 belongs',
+          f'    // to one ordering and is formed by that ordering\'s lane)',
+          f'    static constexpr int NPRE_STORED = {t["plevels"][k - 1][0]};',
           f'    __device__ static __forceinline__ int cur_levels(int i) {{ return {name}_cur_levels[i]; }}',
           f'    __device__ static __forceinline__ int pre_levels(int i) {{ return {name}_pre_levels[i]; }}',
           f'    __device__ static __forceinline__ int cur_mask(int c) {{ return {name}_cur_mask[c]; }}',
