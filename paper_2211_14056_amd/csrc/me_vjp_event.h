@@ -44,13 +44,14 @@ struct KinStore {
 };
 
 // g[k] += zbar . dz/d(direction k) for each kinematic input as it is formed
-template <typename R, int NZ, int CH>
+// (zbar of slot s at zb[s * ZS])
+template <typename R, int ZS, int CH>
 struct KinContract {
-    const R (&zb)[NZ];
+    const R* zb;
     double g[CH];
     __device__ __forceinline__ void put(int s, const DualN<double, CH>& v)
     {
-        const double w = double(zb[s]);
+        const double w = double(zb[s * ZS]);
 #pragma unroll
         for (int k = 0; k < CH; ++k) g[k] = fma(w, v.t[k], g[k]);
     }
@@ -72,15 +73,16 @@ __device__ __forceinline__ void event_momenta(const KT (&P)[NOUT][4], double rs,
 // |M|^2 without couplings and normalisation (me) and its derivatives grad[0..D-1]
 // along x and grad[D] along m_t, for the uniforms x of one event.  edges: Vegas
 // grid [D][nb + 1] or null (identity map).  CH: tangent directions per
-// kinematic pass (ceil((D + 1)/CH) passes).
-template <int K, typename R, int CH>
+// kinematic pass (ceil((D + 1)/CH) passes).  zb: the adjoint's accumulators,
+// max(NZ, NZB) slots at stride ZS (the first NZ hold zbar on return), owned by
+// the caller: registers of the lane (ZS = 1) or its column of an LDS array.
+template <int K, typename R, int CH, int ZS>
 __device__ __forceinline__ void vjp_event(const double (&x)[3 * K - 4], const double* edges, int nb, double rs,
-                                          double mt, double& me, double (&grad)[3 * K - 3])
+                                          double mt, double& me, double (&grad)[3 * K - 3], R* zb)
 {
     constexpr int NOUT = K, NEXT = K + 2, D = 3 * K - 4;
     typedef AdjProc<K> A;
     constexpr int NZ = A::NZ;
-    R zb[NZ];
     {
         double y[D];
         double jac = 1.0;
@@ -100,12 +102,13 @@ __device__ __forceinline__ void vjp_event(const double (&x)[3 * K - 4], const do
         KinStore<R, NZ> st{z};
         A::kin(pe, mt, st);
         R acc = R(0);
-        A::template adjoint<R>(z, zb, acc);
+        A::template adjoint<R, ZS>(z, zb, acc);
         me = double(acc);
     }
     typedef DualN<double, CH> DN;
-#pragma unroll
-    for (int c0 = 0; c0 <= D; c0 += CH) {      // unrolled: every index and seed is a constant
+    // one pass at a time: unrolled, the passes' tangent values were live together and spilled
+#pragma unroll 1
+    for (int c0 = 0; c0 <= D; c0 += CH) {
         DN y[D];
         double jac = 1.0;
 #pragma unroll
@@ -122,11 +125,13 @@ __device__ __forceinline__ void vjp_event(const double (&x)[3 * K - 4], const do
         rambo_event<NOUT, DN>(y, rs, m, P, nullptr);
         DN pe[NEXT][4];
         event_momenta<NOUT, DN>(P, rs, pe);
-        KinContract<R, NZ, CH> kc{zb, {}};
+        KinContract<R, ZS, CH> kc{zb, {}};
         A::kin(pe, mtd, kc);
 #pragma unroll
-        for (int k = 0; k < CH; ++k)
-            if (c0 + k <= D) grad[c0 + k] = kc.g[k];
+        for (int i = 0; i <= D; ++i)           // constant indices: grad stays in registers
+#pragma unroll
+            for (int k = 0; k < CH; ++k)
+                if (c0 + k == i) grad[i] = kc.g[k];
     }
 }
 

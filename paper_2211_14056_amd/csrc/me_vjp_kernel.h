@@ -19,11 +19,11 @@
 
 namespace mf {
 
-// tangent directions per kinematic pass: three (gg -> ttbar: all d + 1 = 3 at once;
-// gg -> ttbar g: two passes; gg -> ttbar gg: three).  Measured on 4e6 gg -> ttbar g
-// events, the tangent stage takes 1.29 ms with three directions per pass, 1.60 ms with
-// two and 3.28 ms with all six at once (the wide tangents spill).
-constexpr int vjp_tangent_width(int k) { return 3; }
+// tangent directions per kinematic pass, one pass at a time.  Measured on 4e6
+// gg -> ttbar g events (whole derivative): FP32 recursion 8.27 ms with three
+// directions per pass, 8.96 with two, 10.76 with one; FP64 recursion (whose adjoint
+// still spills) 38.5 ms with one direction per pass, 40.4 with two, 42.2 with three.
+template <typename R> constexpr int vjp_tangent_width() { return sizeof(R) == 8 ? 1 : 3; }
 
 // derivative of event e of request q (shared settings in j)
 template <int PROC, typename R>
@@ -36,7 +36,15 @@ __device__ __forceinline__ void vjp_one_event(const VjpJob& j, const VjpReq& q, 
 #pragma unroll
     for (int k = 0; k < D; ++k) x[k] = q.x[k * n + e];
     double me, g[D + 1];
-    vjp_event<K, R, vjp_tangent_width(K)>(x, j.edges, j.nb, j.sqrt_s, j.mt, me, g);
+    typedef AdjProc<K> A;
+    if constexpr (A::NZB > 0) {
+        // accumulators in LDS: slot s of lane l at zbl[s * 64 + l] (one-wave blocks)
+        __shared__ R zbl[A::NZB * 64];
+        vjp_event<K, R, vjp_tangent_width<R>(), 64>(x, j.edges, j.nb, j.sqrt_s, j.mt, me, g, zbl + threadIdx.x);
+    } else {
+        R zbr[A::NZ];
+        vjp_event<K, R, vjp_tangent_width<R>(), 1>(x, j.edges, j.nb, j.sqrt_s, j.mt, me, g, zbr);
+    }
     const double scale = j.coupling * AdjProc<K>::norm;
     const double gbar = q.grad_me[e];
     const double gs = gbar * scale;

@@ -757,8 +757,8 @@ def _adj_lvalue(n):
     return n[:i] + '_b' + n[i:]
 
 
-def _regrouped_quark_sweeps(proc, ir, g_read, ext_adj, group_barriers):
-    """Reverse sweep of the quark line by groups of orderings with the same first gluon.
+def _regrouped_quark_sweeps(proc, ir, g_read, ext_adj, group_barriers, jb_mem=False, depth=1):
+    """Reverse sweep of the quark line by groups of orderings with the same first `depth` gluons.
 
     The forward quark line and colour sums have run; the colour sums' sweep gives the
     adjoints of the amplitudes.  Per group, the statements its amplitudes depend on are
@@ -782,8 +782,12 @@ def _regrouped_quark_sweeps(proc, ir, g_read, ext_adj, group_barriers):
             e = m.group(2)
             flops_of[m.group(1)] = 2 if e.startswith('fma(') else (1 if (' + ' in e or ' * ' in e) else 0)
     lines, rec_flops, sweep_flops = [], 0, 0
-    for g in range(proc.k):
-        outs = [ir.amps[h][si] for h in range(2) for si, sig in enumerate(proc.orderings) if sig[0] == g]
+    keys = []
+    for sig in proc.orderings:
+        if tuple(sig[:depth]) not in keys:
+            keys.append(tuple(sig[:depth]))
+    for gi, key in enumerate(keys):
+        outs = [ir.amps[h][si] for h in range(2) for si, sig in enumerate(proc.orderings) if tuple(sig[:depth]) == key]
         need = set()
         stack = [base_sign(x)[0] for a in outs for x in (a.re, a.im) if not x.is_const]
         while stack:
@@ -794,7 +798,7 @@ def _regrouped_quark_sweeps(proc, ir, g_read, ext_adj, group_barriers):
             for x in ops[n][2]:
                 if not x.is_const:
                     stack.append(base_sign(x)[0])
-        pfx = f'q{g}_'
+        pfx = f'q{gi}_'
         ren = lambda n: pfx + n if n in need else n          # noqa: E731
 
         def rn(x):
@@ -805,10 +809,21 @@ def _regrouped_quark_sweeps(proc, ir, g_read, ext_adj, group_barriers):
         sub = [n for n in order if n in need]
         if group_barriers:
             lines.append('__builtin_amdgcn_sched_barrier(0);')
+        # the group's copy of the top spinor row, opaque to the compiler: every quark-line
+        # value depends on it, so the recomputation cannot be merged with the forward pass
+        # (which would keep the forward values live until the sweep instead)
+        lines.append(f'cplx<R> {pfx}ubs[4];')
+        for j in range(4):
+            lines.append(f'{pfx}ubs[{j}] = ubs[{j}]; opaque({pfx}ubs[{j}].re); opaque({pfx}ubs[{j}].im);')
         for n in sub:
-            lines.append(_re.sub(r'\bu(\d+)\b', lambda m: ren('u' + m.group(1)), text[n]))
+            l = _re.sub(r'\bu(\d+)\b', lambda m: ren('u' + m.group(1)), text[n])
+            lines.append(_re.sub(r'\bubs\[', f'{pfx}ubs[', l))
             rec_flops += flops_of.get(n, 0)
-        a = Adjoint({ren(n) for n in sub} | set(g_read), ext_adj, declared=g_read)
+        val = lambda n: pfx + n if n.startswith('ubs[') else n          # noqa: E731
+        if jb_mem:
+            a = Adjoint({ren(n) for n in sub}, ext_adj, val=val)
+        else:
+            a = Adjoint({ren(n) for n in sub} | set(g_read), ext_adj, declared=g_read, val=val)
         for amp in outs:
             for x in (amp.re, amp.im):
                 if not x.is_const:
@@ -821,7 +836,8 @@ def _regrouped_quark_sweeps(proc, ir, g_read, ext_adj, group_barriers):
     return lines, rec_flops, sweep_flops
 
 
-def emit_qcd_adjoint(proc, opaque_inputs=True, group_barriers=True, regroup=False):
+def emit_qcd_adjoint(proc, opaque_inputs=True, group_barriers=True, regroup=False, zb_mem=False, jb_mem=False,
+                     group_depth=1):
     """Adjoint (reverse sweep) of the helicity-summed, colour-contracted |M|^2 with respect
     to the kinematic inputs z (emit_kin), recomputing every current per helicity.
 
@@ -830,7 +846,16 @@ def emit_qcd_adjoint(proc, opaque_inputs=True, group_barriers=True, regroup=Fals
     antitop helicities, which adds into the adjoints of the currents and of z; after the
     top-helicity loop the gluon currents are recomputed (no value of the first pass is
     kept across the loop except the currents the quark line reads) and swept backwards.
-    Nothing is stored in memory.  Returns (source, flop counts)."""
+    No current is stored in memory.
+
+    regroup: after the colour sums' sweep, the quark line is swept by groups of orderings
+    sharing their first `group_depth` gluons, each group's values recomputed
+    (_regrouped_quark_sweeps); otherwise the whole quark line is swept at once.
+    zb_mem: the adjoints of z accumulate in place in the caller's array zb (slot i at
+    zb[i * ZS]; ZS = 64 puts one lane's slots a wavefront apart in LDS) instead of in
+    registers.  jb_mem (with zb_mem): the adjoints of the gluon currents the quark line
+    reads accumulate there too, after the z slots, and are loaded back for the gluon
+    sweep.  Returns (source, flop counts)."""
     from .adjoint import Adjoint, base_sign, operand_names, defined_names
     k = proc.k
     ir = _build_ir(proc, 0, False, False, group_barriers)
@@ -845,10 +870,34 @@ def emit_qcd_adjoint(proc, opaque_inputs=True, group_barriers=True, regroup=Fals
     out = [kin_src, '']
     out.append(f'// adjoint of {fn}: |M|^2 (no couplings, no normalisation) added to me, its gradient')
     out.append(f'// with respect to the kinematic inputs z written to zb')
-    out.append('template <typename R>')
-    out.append(f'__device__ __forceinline__ void {fn}_adjoint(const R (&z)[{len(slots)}], R (&zb)[{len(slots)}], R& me)')
+    nz = len(slots)
+    zidx = {n: i for i, n in enumerate(slots)}
+    jidx = {n: nz + j for j, n in enumerate(g_read)} if jb_mem else {}
+    nzb = nz + len(jidx)
+    if zb_mem:
+        out.append(f'// (in place: slot i at zb[i * ZS], {nzb} slots: the {nz} inputs'
+                   + (f', then the {len(jidx)} current components the quark line reads)' if jb_mem else ')'))
+        out.append('template <typename R, int ZS>')
+        out.append(f'__device__ __forceinline__ void {fn}_adjoint(const R (&z)[{nz}], R* zb, R& me)')
+    else:
+        out.append('template <typename R>')
+        out.append(f'__device__ __forceinline__ void {fn}_adjoint(const R (&z)[{nz}], R (&zb)[{nz}], R& me)')
     out.append('{')
     body = []
+
+    def zlv(n):
+        """lvalue of the adjoint of input n (None: no derivative)"""
+        if not zb_mem:
+            return _adj_lvalue(n)
+        if n.startswith('lam'):
+            return None
+        if n in zidx:
+            return f'zb[{zidx[n]} * ZS]'
+        if n in jidx:
+            return f'zb[{jidx[n]} * ZS]'
+        return _adj_lvalue(n)                 # ubs: the current top helicity's row, local
+    if zb_mem:
+        body += [f'zb[{i} * ZS] = R(0);' for i in range(nz)]
     # unpack z into the names the recursion reads; accumulators for their adjoints
     arrays = {}
     scalars = []
@@ -862,16 +911,19 @@ def emit_qcd_adjoint(proc, opaque_inputs=True, group_barriers=True, regroup=Fals
     for base, items in arrays.items():
         if base in ('ub', 'vs'):
             body.append(f'cplx<R> {base}[2][4] = {{}};')
-            body.append(f'cplx<R> {base}_b[2][4] = {{}};')
+            if not zb_mem:
+                body.append(f'cplx<R> {base}_b[2][4] = {{}};')
         else:
             size = max(int(n[len(base) + 1:].split(']')[0]) for n, _ in items) + 1
             body.append(f'R {base}[{size}] = {{}};')
-            body.append(f'R {base}_b[{size}] = {{}};')
+            if not zb_mem:
+                body.append(f'R {base}_b[{size}] = {{}};')
         for n, i in items:
             body.append(f'{n} = z[{i}];')
     for n, i in scalars:
         body.append(f'const R {n} = z[{i}];')
-        body.append(f'R {n}_b = R(0);')
+        if not zb_mem:
+            body.append(f'R {n}_b = R(0);')
     opq = []
     if opaque_inputs:
         for gi, leg in enumerate(proc.gl_legs):
@@ -884,7 +936,12 @@ def emit_qcd_adjoint(proc, opaque_inputs=True, group_barriers=True, regroup=Fals
     for gi in range(k):
         body.append(f'    const R lam{gi} = (gconf >> {gi}) & 1 ? R(1) : R(-1);')
     body += ['    ' + l for l in ir.gluon_lines]
-    body += [f'    R {n}_b = R(0);' for n in g_read]
+    if jb_mem:
+        body += [f'    zb[{jidx[n]} * ZS] = R(0);' for n in g_read]
+    else:
+        body += [f'    R {n}_b = R(0);' for n in g_read]
+    q_temps_extra = set() if jb_mem else set(g_read)      # current adjoints held as locals
+    q_declared = () if jb_mem else g_read
     body.append('    #pragma unroll 1')
     body.append('    for (int ht = 0; ht < 2; ++ht) {')
     body += ['        ' + l for l in opq]
@@ -899,30 +956,40 @@ def emit_qcd_adjoint(proc, opaque_inputs=True, group_barriers=True, regroup=Fals
     if regroup:
         # colour sums backwards to the amplitudes, then the quark line group by group
         amp_names = {base_sign(x)[0] for row in ir.amps for a in row for x in (a.re, a.im) if not x.is_const}
-        aq = Adjoint(set(defined_names(cs.ops)) | amp_names, _adj_lvalue)
+        aq = Adjoint(set(defined_names(cs.ops)) | amp_names, zlv)
         for h in range(2):
             aq.seed(ir.csq[h], 'R(1)')
         aq.sweep(cs.ops)
         if group_barriers:
             body.append('        __builtin_amdgcn_sched_barrier(0);')
         body += ['        ' + l for l in aq.lines]
-        glines, rec_q, sw = _regrouped_quark_sweeps(proc, ir, g_read, _adj_lvalue, group_barriers)
+        glines, rec_q, sw = _regrouped_quark_sweeps(proc, ir, g_read, zlv, group_barriers, jb_mem=jb_mem,
+                                                    depth=group_depth)
         body += ['        ' + l for l in glines]
         aq.flops += sw
     else:
-        aq = Adjoint(set(qc_temps) | set(g_read), _adj_lvalue, declared=g_read)
+        aq = Adjoint(set(qc_temps) | q_temps_extra, zlv, declared=q_declared)
         for h in range(2):
             aq.seed(ir.csq[h], 'R(1)')
         aq.sweep(qc_ops)
         if group_barriers:
             body.append('        __builtin_amdgcn_sched_barrier(0);')
         body += ['        ' + l for l in aq.lines]
-    body.append('        for (int j = 0; j < 4; ++j) {')
-    body.append('            cplx<R>& t = ht ? ub_b[1][j] : ub_b[0][j];')
-    body.append('            t.re += ubs_b[j].re;')
-    body.append('            t.im += ubs_b[j].im;')
-    body.append('        }')
+    if zb_mem:
+        for j in range(4):
+            for part in ('re', 'im'):
+                i0, i1 = zidx.get(f'ub[0][{j}].{part}'), zidx.get(f'ub[1][{j}].{part}')
+                if i0 is not None:
+                    body.append(f'        {{ R& t = zb[(ht ? {i1} : {i0}) * ZS]; t = t + ubs_b[{j}].{part}; }}')
+    else:
+        body.append('        for (int j = 0; j < 4; ++j) {')
+        body.append('            cplx<R>& t = ht ? ub_b[1][j] : ub_b[0][j];')
+        body.append('            t.re += ubs_b[j].re;')
+        body.append('            t.im += ubs_b[j].im;')
+        body.append('        }')
     body.append('    }')
+    if jb_mem:
+        body += [f'    R {n}_b = zb[{jidx[n]} * ZS];' for n in g_read]
     # recompute the gluon currents (renamed), then sweep them backwards
     import re as _re
     ren = lambda n: 'tr' + n[1:] if n in g_set else n       # noqa: E731
@@ -930,15 +997,16 @@ def emit_qcd_adjoint(proc, opaque_inputs=True, group_barriers=True, regroup=Fals
     if group_barriers:
         body.append('    __builtin_amdgcn_sched_barrier(0);')
     body += ['    ' + l for l in rec_lines]
-    ag = Adjoint(g_set, _adj_lvalue, declared=g_read, val=ren)
+    ag = Adjoint(g_set, zlv, declared=g_read, val=ren)
     ag.sweep(b.ops)
     body += ['    ' + l for l in ag.lines]
     body.append('}')
-    for i, n in enumerate(slots):
-        if n.startswith(('ub[', 'vs[')):
-            body.append(f'zb[{i}] = {n[:2]}_b{n[2:]};')
-        else:
-            body.append(f'zb[{i}] = {_adj_lvalue(n)};')
+    if not zb_mem:
+        for i, n in enumerate(slots):
+            if n.startswith(('ub[', 'vs[')):
+                body.append(f'zb[{i}] = {n[:2]}_b{n[2:]};')
+            else:
+                body.append(f'zb[{i}] = {_adj_lvalue(n)};')
     out += ['    ' + l for l in body]
     out.append('}')
     per_gconf = 2 * ir.gluon_flops + ag.flops + 2 * (ir.quark_flops + rec_q + ir.colour_flops + 1 + aq.flops)
@@ -951,12 +1019,14 @@ def emit_qcd_adjoint(proc, opaque_inputs=True, group_barriers=True, regroup=Fals
             'template <int K> struct AdjProc;',
             f'template <> struct AdjProc<{k}> {{',
             f'    static constexpr int NZ = {len(slots)};',
+            f'    static constexpr int NZB = {nzb if zb_mem else 0};        // slots of zb in memory (0: registers)',
             '    template <typename KT, typename Out>',
             f'    __device__ static __forceinline__ void kin(const KT (&p)[{n}][4], const KT mt, Out& o) '
             f'{{ {fn}_kin<KT>(p, mt, o); }}',
-            '    template <typename R>',
-            f'    __device__ static __forceinline__ void adjoint(const R (&z)[NZ], R (&zb)[NZ], R& me) '
-            f'{{ {fn}_adjoint<R>(z, zb, me); }}',
+            '    template <typename R, int ZS>',
+            f'    __device__ static __forceinline__ void adjoint(const R (&z)[NZ], R* zb, R& me) '
+            + (f'{{ {fn}_adjoint<R, ZS>(z, zb, me); }}' if zb_mem else
+               f'{{ {fn}_adjoint<R>(z, *reinterpret_cast<R (*)[NZ]>(zb), me); }}'),
             '    // 2 (reversed helicities) / (initial average * identical final gluons * colour denominator)',
             f'    static constexpr double norm = 2.0 / ({proc.avg!r} * {float(proc.sym)!r} * {float(proc.cden)!r});',
             '};',
@@ -990,6 +1060,20 @@ SHARE_F64 = False
 # on the GPU, while the same source is exact on the CPU.  Without them it has
 # no spill and is deterministic; it costs 6%.
 SHARE_F32_VALU = False
+
+
+# The derivative kernels: the adjoints of z accumulate in LDS (zb_mem) and the quark
+# line is swept one colour ordering at a time, each recomputed from an opaque copy of
+# the top spinor (regroup, group_depth = number of gluons).  Measured against the
+# register form with the whole quark line swept at once: gg -> ttbar g 9.81 -> 8.27 ms
+# (FP32) and 47.3 -> 38.5 ms (FP64) on 4e6 events; gg -> ttbar gg 39.6 -> 28.6 ms
+# (FP32) on 2^18 events.  Accumulating the current adjoints in LDS as well (jb_mem)
+# needs more LDS than leaves four waves per compute unit.
+ADJ_OPTS = {
+    'gg_tt': dict(zb_mem=True, regroup=True, group_depth=2),
+    'gg_ttg': dict(zb_mem=True, regroup=True, group_depth=3),
+    'gg_ttgg': dict(zb_mem=True, regroup=True, group_depth=4),
+}
 
 
 def _variant(proc, name, suffix, **kw):
@@ -1052,7 +1136,7 @@ def emit_all(outdir, **opts):
                         f'{{ return 2.0 / ({proc.avg!r} * {float(proc.sym)!r} * {float(proc.cden)!r}); }}\n')
             flops['pair_executed_per_event'] = info_p['executed_per_event']
         # reverse-sweep derivative: kinematic inputs and the adjoint of the recursion
-        src_adj, info_adj = emit_qcd_adjoint(proc)
+        src_adj, info_adj = emit_qcd_adjoint(proc, **ADJ_OPTS[name])
         with open(os.path.join(outdir, f'me_{name}_adj.inc'), 'w') as f:
             f.write('// Generated by paper_2211_14056_amd.gen.process_compiler -- do not edit.\n')
             f.write(src_adj + '\n')

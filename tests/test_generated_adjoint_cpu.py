@@ -61,7 +61,9 @@ int main()
         double x[D];
         for (int k = 0; k < D; ++k) if (scanf("%lf", &x[k]) != 1) return 3;
         double me, g[D + 1];
-        mf::vjp_event<KG, RT, CHW>(x, edges, nb, rs, mt, me, g);
+        typedef mf::AdjProc<KG> A;
+        RT zb[A::NZB > A::NZ ? A::NZB : A::NZ];
+        mf::vjp_event<KG, RT, CHW, 1>(x, edges, nb, rs, mt, me, g, zb);
         printf("%.17g", me);
         for (int k = 0; k <= D; ++k) printf(" %.17g", g[k]);
         printf("\n");
@@ -96,29 +98,40 @@ def _norms(proc):
     return g2 ** gp.k * 2.0 / (gp.avg * gp.sym * gp.cden)
 
 
+RG = dict(regroup=True)
+ZB = dict(zb_mem=True, regroup=True)
 CASES = [
-    # (process, working type, tangent directions per kinematic pass, events, quark line swept by groups)
-    ('gg_tt', 'double', 3, 16, False),
-    ('gg_ttg', 'double', 6, 16, False),
-    ('gg_ttg', 'double', 2, 6, False),
-    ('gg_ttg', 'float', 6, 16, False),
-    ('gg_ttgg', 'double', 3, 3, False),
-    ('gg_ttgg', 'float', 9, 3, False),
-    ('gg_tt', 'double', 3, 8, True),
-    ('gg_ttg', 'double', 3, 16, True),
-    ('gg_ttg', 'float', 3, 16, True),
-    ('gg_ttgg', 'double', 3, 3, True),
+    # (process, working type, tangent directions per kinematic pass, events, emitter options):
+    # accumulators in registers or in the caller's memory (zb_mem; jb_mem: the current
+    # adjoints too), quark line swept at once or by groups of orderings sharing their
+    # first group_depth gluons (regroup)
+    ('gg_tt', 'double', 3, 16, {}),
+    ('gg_ttg', 'double', 6, 16, {}),
+    ('gg_ttg', 'double', 2, 6, {}),
+    ('gg_ttg', 'float', 6, 16, {}),
+    ('gg_ttgg', 'double', 3, 3, {}),
+    ('gg_ttgg', 'float', 9, 3, {}),
+    ('gg_tt', 'double', 3, 8, RG),
+    ('gg_ttg', 'double', 3, 16, RG),
+    ('gg_ttg', 'float', 3, 16, RG),
+    ('gg_ttgg', 'double', 3, 3, RG),
+    ('gg_tt', 'double', 1, 8, dict(ZB, group_depth=2)),
+    ('gg_ttg', 'double', 1, 16, dict(ZB, group_depth=3)),
+    ('gg_ttg', 'float', 3, 16, dict(ZB, group_depth=3)),
+    ('gg_ttg', 'double', 2, 8, dict(zb_mem=True, jb_mem=True)),
+    ('gg_ttgg', 'double', 1, 3, dict(ZB, group_depth=4)),
+    ('gg_ttgg', 'float', 3, 3, dict(ZB, group_depth=2, jb_mem=True)),
 ]
 
 
 @pytest.mark.skipif(shutil.which('g++') is None, reason='needs a host C++ compiler')
-@pytest.mark.parametrize('proc,rtype,ch,n,regroup', CASES)
-def test_generated_adjoint_on_cpu_matches_oracle_gradient(tmp_path, proc, rtype, ch, n, regroup):
+@pytest.mark.parametrize('proc,rtype,ch,n,opts', CASES)
+def test_generated_adjoint_on_cpu_matches_oracle_gradient(tmp_path, proc, rtype, ch, n, opts):
     d_ = str(tmp_path)
     _host_headers(d_)
     legs = processes.PROCESSES[proc]['n_ext']
     gp = pc.GGTTProcess(proc, legs)
-    body, _ = pc.emit_qcd_adjoint(gp, regroup=regroup)
+    body, _ = pc.emit_qcd_adjoint(gp, **opts)
     open(os.path.join(d_, 'body.inc'), 'w').write(body + '\n')
     open(os.path.join(d_, 'driver.cpp'), 'w').write(DRIVER)
     exe = os.path.join(d_, 'vjp')
