@@ -757,14 +757,15 @@ def _adj_lvalue(n):
     return n[:i] + '_b' + n[i:]
 
 
-def _regrouped_quark_sweeps(proc, ir, g_read, ext_adj, group_barriers, jb_mem=False, depth=1):
+def _regrouped_quark_sweeps(proc, ir, g_read, ext_adj, group_barriers, depth=1):
     """Reverse sweep of the quark line by groups of orderings with the same first `depth` gluons.
 
     The forward quark line and colour sums have run; the colour sums' sweep gives the
     adjoints of the amplitudes.  Per group, the statements its amplitudes depend on are
     emitted again under new names (recomputation) and swept backwards from those adjoints,
-    so only one group's quark-line values are live during a sweep.  Returns (lines, flops
-    of the recomputation, flops of the sweeps)."""
+    so only one group's quark-line values are live during a sweep.  g_read: the gluon-current
+    components whose adjoints are locals (any other input's goes through ext_adj).  Returns
+    (lines, flops of the recomputation, flops of the sweeps)."""
     import re as _re
     from .adjoint import Adjoint, base_sign
     q = ir.q
@@ -820,10 +821,7 @@ def _regrouped_quark_sweeps(proc, ir, g_read, ext_adj, group_barriers, jb_mem=Fa
             lines.append(_re.sub(r'\bubs\[', f'{pfx}ubs[', l))
             rec_flops += flops_of.get(n, 0)
         val = lambda n: pfx + n if n.startswith('ubs[') else n          # noqa: E731
-        if jb_mem:
-            a = Adjoint({ren(n) for n in sub}, ext_adj, val=val)
-        else:
-            a = Adjoint({ren(n) for n in sub} | set(g_read), ext_adj, declared=g_read, val=val)
+        a = Adjoint({ren(n) for n in sub} | set(g_read), ext_adj, declared=g_read, val=val)
         for amp in outs:
             for x in (amp.re, amp.im):
                 if not x.is_const:
@@ -855,7 +853,8 @@ def emit_qcd_adjoint(proc, opaque_inputs=True, group_barriers=True, regroup=Fals
     zb[i * ZS]; ZS = 64 puts one lane's slots a wavefront apart in LDS) instead of in
     registers.  jb_mem (with zb_mem): the adjoints of the gluon currents the quark line
     reads accumulate there too, after the z slots, and are loaded back for the gluon
-    sweep.  Returns (source, flop counts)."""
+    sweep (True: all of them; a number: that many, the least read ones).  Returns
+    (source, flop counts)."""
     from .adjoint import Adjoint, base_sign, operand_names, defined_names
     k = proc.k
     ir = _build_ir(proc, 0, False, False, group_barriers)
@@ -872,7 +871,17 @@ def emit_qcd_adjoint(proc, opaque_inputs=True, group_barriers=True, regroup=Fals
     out.append(f'// with respect to the kinematic inputs z written to zb')
     nz = len(slots)
     zidx = {n: i for i, n in enumerate(slots)}
-    jidx = {n: nz + j for j, n in enumerate(g_read)} if jb_mem else {}
+    if jb_mem is True:
+        jb_names = list(g_read)
+    elif jb_mem:
+        # the jb_mem current components the quark line reads least often
+        from collections import Counter
+        uses = Counter(base_sign(x)[0] for _, _, ops_ in qc_ops for x in ops_ if not x.is_const)
+        jb_names = sorted(sorted(g_read, key=lambda n: (uses[n], int(n[1:])))[:int(jb_mem)], key=lambda n: int(n[1:]))
+    else:
+        jb_names = []
+    jidx = {n: nz + j for j, n in enumerate(jb_names)}
+    g_reg = [n for n in g_read if n not in jidx]          # current adjoints held as locals
     nzb = nz + len(jidx)
     if zb_mem:
         out.append(f'// (in place: slot i at zb[i * ZS], {nzb} slots: the {nz} inputs'
@@ -936,12 +945,10 @@ def emit_qcd_adjoint(proc, opaque_inputs=True, group_barriers=True, regroup=Fals
     for gi in range(k):
         body.append(f'    const R lam{gi} = (gconf >> {gi}) & 1 ? R(1) : R(-1);')
     body += ['    ' + l for l in ir.gluon_lines]
-    if jb_mem:
-        body += [f'    zb[{jidx[n]} * ZS] = R(0);' for n in g_read]
-    else:
-        body += [f'    R {n}_b = R(0);' for n in g_read]
-    q_temps_extra = set() if jb_mem else set(g_read)      # current adjoints held as locals
-    q_declared = () if jb_mem else g_read
+    body += [f'    zb[{jidx[n]} * ZS] = R(0);' for n in jb_names]
+    body += [f'    R {n}_b = R(0);' for n in g_reg]
+    q_temps_extra = set(g_reg)
+    q_declared = g_reg
     body.append('    #pragma unroll 1')
     body.append('    for (int ht = 0; ht < 2; ++ht) {')
     body += ['        ' + l for l in opq]
@@ -963,8 +970,7 @@ def emit_qcd_adjoint(proc, opaque_inputs=True, group_barriers=True, regroup=Fals
         if group_barriers:
             body.append('        __builtin_amdgcn_sched_barrier(0);')
         body += ['        ' + l for l in aq.lines]
-        glines, rec_q, sw = _regrouped_quark_sweeps(proc, ir, g_read, zlv, group_barriers, jb_mem=jb_mem,
-                                                    depth=group_depth)
+        glines, rec_q, sw = _regrouped_quark_sweeps(proc, ir, g_reg, zlv, group_barriers, depth=group_depth)
         body += ['        ' + l for l in glines]
         aq.flops += sw
     else:
@@ -988,8 +994,7 @@ def emit_qcd_adjoint(proc, opaque_inputs=True, group_barriers=True, regroup=Fals
         body.append('            t.im += ubs_b[j].im;')
         body.append('        }')
     body.append('    }')
-    if jb_mem:
-        body += [f'    R {n}_b = zb[{jidx[n]} * ZS];' for n in g_read]
+    body += [f'    R {n}_b = zb[{jidx[n]} * ZS];' for n in jb_names]
     # recompute the gluon currents (renamed), then sweep them backwards
     import re as _re
     ren = lambda n: 'tr' + n[1:] if n in g_set else n       # noqa: E731
@@ -1067,11 +1072,14 @@ SHARE_F32_VALU = False
 # the top spinor (regroup, group_depth = number of gluons).  Measured against the
 # register form with the whole quark line swept at once: gg -> ttbar g 9.81 -> 8.27 ms
 # (FP32) and 47.3 -> 38.5 ms (FP64) on 4e6 events; gg -> ttbar gg 39.6 -> 28.6 ms
-# (FP32) on 2^18 events.  Accumulating the current adjoints in LDS as well (jb_mem)
-# needs more LDS than leaves four waves per compute unit.
+# (FP32) and 93.2 -> 82.5 ms (FP64) on 2^18 events.  For gg -> ttbar g, the 20 least
+# read current adjoints in LDS too (jb_mem; 39.9 KB per wave in FP64, the most that
+# leaves four waves per compute unit): FP64 38.6 -> 33.3 ms, FP32 unchanged (8.25 vs
+# 8.36 ms).  For gg -> ttbar gg, 78 of them (40 KB per wave in FP32) was slower
+# (28.5 -> 29.2 ms), and in FP64 its z slots alone take 42 KB.
 ADJ_OPTS = {
     'gg_tt': dict(zb_mem=True, regroup=True, group_depth=2),
-    'gg_ttg': dict(zb_mem=True, regroup=True, group_depth=3),
+    'gg_ttg': dict(zb_mem=True, regroup=True, group_depth=3, jb_mem=20),
     'gg_ttgg': dict(zb_mem=True, regroup=True, group_depth=4),
 }
 
