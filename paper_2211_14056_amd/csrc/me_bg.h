@@ -280,20 +280,42 @@ __device__ double bg_event(const double (&pe)[K + 2][4], double mt, BgShared<K, 
                 }
             }
             __syncthreads();
-            // ---- colour sum: lane takes rows i of C' (integer numerators; C' symmetric,
-            // so row i is read as column i, coalesced across lanes)
-            for (int i = lane; i < T::NORD; i += LPE) {
-                R y[2][2] = {{R(0), R(0)}, {R(0), R(0)}};
+            // ---- colour sum: lane takes the rows i = lane + r * LPE of C' (integer numerators;
+            // C' symmetric, so row i is read as column i, coalesced across lanes) and runs over
+            // the orderings j once for all its rows, each amplitude read from LDS once
+            {
+                constexpr int RP = (T::NORD + LPE - 1) / LPE;
+                R y[RP][2][2];
+#pragma unroll
+                for (int r = 0; r < RP; ++r)
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) y[r][h][0] = y[r][h][1] = R(0);
                 for (int j = 0; j < T::NORD; ++j) {
-                    const R c = R(T::cnum(j, i));
+                    R a[2][2];
 #pragma unroll
                     for (int h = 0; h < 2; ++h) {
-                        y[h][0] = fma(c, sh.A[h][j][0], y[h][0]);
-                        y[h][1] = fma(c, sh.A[h][j][1], y[h][1]);
+                        a[h][0] = sh.A[h][j][0];
+                        a[h][1] = sh.A[h][j][1];
+                    }
+#pragma unroll
+                    for (int r = 0; r < RP; ++r) {
+                        const R c = R(T::cnum(j, lane + r * LPE));      // 0 past the last row
+#pragma unroll
+                        for (int h = 0; h < 2; ++h) {
+                            y[r][h][0] = fma(c, a[h][0], y[r][h][0]);
+                            y[r][h][1] = fma(c, a[h][1], y[r][h][1]);
+                        }
                     }
                 }
 #pragma unroll
-                for (int h = 0; h < 2; ++h) acc = fma(sh.A[h][i][0], y[h][0], fma(sh.A[h][i][1], y[h][1], acc));
+                for (int r = 0; r < RP; ++r) {
+                    const int i = lane + r * LPE;
+                    if (i < T::NORD) {
+#pragma unroll
+                        for (int h = 0; h < 2; ++h)
+                            acc = fma(sh.A[h][i][0], y[r][h][0], fma(sh.A[h][i][1], y[r][h][1], acc));
+                    }
+                }
             }
             __syncthreads();
         }

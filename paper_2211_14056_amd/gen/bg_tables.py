@@ -152,8 +152,13 @@ def emit(k, name):
                                      for a, b, s in o['splits']) + '}')
     L.append(f'static __constant__ const short {name}_ord_split[{len(od)}][{k}][3] = {{' + ', '.join(rows) + '};')
     n = len(od)
-    L.append(f'static __constant__ const short {name}_cnum[{n}][{n}] = {{'
-             + ', '.join('{' + ', '.join(str(v) for v in row) + '}' for row in t['cnum']) + '};')
+    # colour numerators as floats (integers, exact), each row padded with zeros to a multiple
+    # of 64 columns: column i of row j is C'[j][i], and a lane reads the columns i = lane + r * LPE
+    # of every row j, r < ceil(n / LPE), whatever the lanes per event
+    cw = -(-n // 64) * 64
+    L.append(f'static __constant__ const float {name}_cnumf[{n}][{cw}] = {{'
+             + ', '.join('{' + ', '.join(f'{float(v)!r}f' for v in list(row) + [0] * (cw - n)) + '}'
+                         for row in t['cnum']) + '};')
     L += ['namespace mf {',
           'template <int K> struct BgTab;',
           f'template <> struct BgTab<{k}> {{',
@@ -171,7 +176,7 @@ def emit(k, name):
           f'    __device__ static __forceinline__ int pre_mask(int q) {{ return {name}_pre_mask[q]; }}',
           f'    __device__ static __forceinline__ const short* pre_split(int q, int s) {{ return {name}_pre_split[q][s]; }}',
           f'    __device__ static __forceinline__ const short* ord_split(int o, int s) {{ return {name}_ord_split[o][s]; }}',
-          f'    __device__ static __forceinline__ int cnum(int i, int j) {{ return {name}_cnum[i][j]; }}',
+          f'    __device__ static __forceinline__ float cnum(int j, int i) {{ return {name}_cnumf[j][i]; }}',
           '};',
           '}  // namespace mf']
     return '\n'.join(L) + '\n', t
