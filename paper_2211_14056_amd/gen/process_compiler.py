@@ -834,8 +834,78 @@ def _regrouped_quark_sweeps(proc, ir, g_read, ext_adj, group_barriers, depth=1):
     return lines, rec_flops, sweep_flops
 
 
+def _ordering_sweeps_with_currents(proc, ir, ext_adj, group_barriers):
+    """Reverse sweep of the quark line and the gluon currents, one colour ordering at a time.
+
+    The forward pass (currents, quark line, colour sums) has run and the colour sums' sweep
+    gives the adjoints of the amplitudes.  Per ordering, the gluon currents and quark-line
+    values its two amplitudes depend on are emitted again under new names, from opaque copies
+    of the helicity signs and of the top spinor (so the compiler can merge them neither with
+    the forward pass nor with another ordering), and swept backwards into the adjoints of the
+    kinematic inputs.  No current or current adjoint lives across orderings.  Returns (lines,
+    flops of the recomputation, flops of the sweeps)."""
+    import re as _re
+    from .adjoint import Adjoint, base_sign
+    allops = ir.b.ops + ir.q.ops
+    ops = {name: (kind, name, operands) for kind, name, operands in allops}
+    order = [name for _, name, _ in allops]
+    text, flops_of = {}, {}
+    for l in ir.gluon_lines + ir.q.lines:
+        m = _re.match(r'const R ([tu]\d+) = (.*);', l)
+        if m:
+            text[m.group(1)] = l
+            e = m.group(2)
+            flops_of[m.group(1)] = 2 if e.startswith('fma(') else (1 if (' + ' in e or ' * ' in e) else 0)
+    lines, rec_flops, sweep_flops = [], 0, 0
+    for si in range(len(proc.orderings)):
+        outs = [ir.amps[h][si] for h in range(2)]
+        need = set()
+        stack = [base_sign(x)[0] for a in outs for x in (a.re, a.im) if not x.is_const]
+        while stack:
+            n = stack.pop()
+            if n in need or n not in ops:
+                continue
+            need.add(n)
+            for x in ops[n][2]:
+                if not x.is_const:
+                    stack.append(base_sign(x)[0])
+        pfx = f'o{si}_'
+        ren = lambda n: pfx + n if n in need else n          # noqa: E731
+
+        def rn(x):
+            if x.is_const:
+                return x
+            b, sgn = base_sign(x)
+            return S(name=ren(b) if sgn > 0 else f'(-{ren(b)})')
+        sub = [n for n in order if n in need]
+        if group_barriers:
+            lines.append('__builtin_amdgcn_sched_barrier(0);')
+        lines.append(f'cplx<R> {pfx}ubs[4];')
+        for j in range(4):
+            lines.append(f'{pfx}ubs[{j}] = ubs[{j}]; opaque({pfx}ubs[{j}].re); opaque({pfx}ubs[{j}].im);')
+        for gi in range(proc.k):
+            lines.append(f'R {pfx}lam{gi} = lam{gi}; opaque({pfx}lam{gi});')
+        for n in sub:
+            l = _re.sub(r'\b([tu]\d+)\b', lambda m: ren(m.group(1)), text[n])
+            l = _re.sub(r'\bubs\[', f'{pfx}ubs[', l)
+            lines.append(_re.sub(r'\blam(\d+)\b', lambda m: f'{pfx}lam{m.group(1)}', l))
+            rec_flops += flops_of.get(n, 0)
+        val = lambda n: pfx + n if n.startswith(('ubs[', 'lam')) else n          # noqa: E731
+        a = Adjoint({ren(n) for n in sub}, ext_adj, val=val)
+        for amp in outs:
+            for x in (amp.re, amp.im):
+                if not x.is_const:
+                    b, sgn = base_sign(x)
+                    a.seed(S(name=ren(b)), f'{b}_b' if sgn > 0 else f'(-{b}_b)')
+        a.sweep([(kind, ren(name), tuple(rn(x) for x in operands)) for kind, name, operands in
+                 (ops[n] for n in sub)])
+        lines += a.lines
+        sweep_flops += a.flops
+    return lines, rec_flops, sweep_flops
+
+
 def emit_qcd_adjoint(proc, opaque_inputs=True, group_barriers=True, regroup=False, zb_mem=False, jb_mem=False,
-                     group_depth=1):
+                     group_depth=1, recompute_currents=False):
     """Adjoint (reverse sweep) of the helicity-summed, colour-contracted |M|^2 with respect
     to the kinematic inputs z (emit_kin), recomputing every current per helicity.
 
@@ -944,9 +1014,11 @@ def emit_qcd_adjoint(proc, opaque_inputs=True, group_barriers=True, regroup=Fals
     body += ['    ' + l for l in opq]
     for gi in range(k):
         body.append(f'    const R lam{gi} = (gconf >> {gi}) & 1 ? R(1) : R(-1);')
-    body += ['    ' + l for l in ir.gluon_lines]
+    if not recompute_currents:
+        body += ['    ' + l for l in ir.gluon_lines]
     body += [f'    zb[{jidx[n]} * ZS] = R(0);' for n in jb_names]
-    body += [f'    R {n}_b = R(0);' for n in g_reg]
+    if not recompute_currents:
+        body += [f'    R {n}_b = R(0);' for n in g_reg]
     q_temps_extra = set(g_reg)
     q_declared = g_reg
     body.append('    #pragma unroll 1')
@@ -956,11 +1028,26 @@ def emit_qcd_adjoint(proc, opaque_inputs=True, group_barriers=True, regroup=Fals
         body.append('        __builtin_amdgcn_sched_barrier(0);')
     body.append('        cplx<R> ubs[4], ubs_b[4] = {};')
     body.append('        for (int j = 0; j < 4; ++j) ubs[j] = ht ? ub[1][j] : ub[0][j];')
+    if recompute_currents:
+        body += ['        ' + l for l in ir.gluon_lines]
     body += ['        ' + l for l in q.lines]
     body += ['        ' + l for l in cs.lines]
     body.append(f'        me += {cs.ref(ir.csq[0])} + {cs.ref(ir.csq[1])};')
     rec_q = 0
-    if regroup:
+    if recompute_currents:
+        # colour sums backwards to the amplitudes, then quark line and currents per ordering
+        amp_names = {base_sign(x)[0] for row in ir.amps for a in row for x in (a.re, a.im) if not x.is_const}
+        aq = Adjoint(set(defined_names(cs.ops)) | amp_names, zlv)
+        for h in range(2):
+            aq.seed(ir.csq[h], 'R(1)')
+        aq.sweep(cs.ops)
+        if group_barriers:
+            body.append('        __builtin_amdgcn_sched_barrier(0);')
+        body += ['        ' + l for l in aq.lines]
+        glines, rec_q, sw = _ordering_sweeps_with_currents(proc, ir, zlv, group_barriers)
+        body += ['        ' + l for l in glines]
+        aq.flops += sw
+    elif regroup:
         # colour sums backwards to the amplitudes, then the quark line group by group
         amp_names = {base_sign(x)[0] for row in ir.amps for a in row for x in (a.re, a.im) if not x.is_const}
         aq = Adjoint(set(defined_names(cs.ops)) | amp_names, zlv)
@@ -995,16 +1082,18 @@ def emit_qcd_adjoint(proc, opaque_inputs=True, group_barriers=True, regroup=Fals
         body.append('        }')
     body.append('    }')
     body += [f'    R {n}_b = zb[{jidx[n]} * ZS];' for n in jb_names]
-    # recompute the gluon currents (renamed), then sweep them backwards
-    import re as _re
-    ren = lambda n: 'tr' + n[1:] if n in g_set else n       # noqa: E731
-    rec_lines = [_re.sub(r'\bt(\d+)\b', r'tr\1', l) for l in ir.gluon_lines]
-    if group_barriers:
-        body.append('    __builtin_amdgcn_sched_barrier(0);')
-    body += ['    ' + l for l in rec_lines]
-    ag = Adjoint(g_set, zlv, declared=g_read, val=ren)
-    ag.sweep(b.ops)
-    body += ['    ' + l for l in ag.lines]
+    ag = Adjoint(g_set, zlv, declared=g_read)
+    if not recompute_currents:
+        # recompute the gluon currents (renamed), then sweep them backwards
+        import re as _re
+        ren = lambda n: 'tr' + n[1:] if n in g_set else n       # noqa: E731
+        rec_lines = [_re.sub(r'\bt(\d+)\b', r'tr\1', l) for l in ir.gluon_lines]
+        if group_barriers:
+            body.append('    __builtin_amdgcn_sched_barrier(0);')
+        body += ['    ' + l for l in rec_lines]
+        ag = Adjoint(g_set, zlv, declared=g_read, val=ren)
+        ag.sweep(b.ops)
+        body += ['    ' + l for l in ag.lines]
     body.append('}')
     if not zb_mem:
         for i, n in enumerate(slots):
@@ -1014,7 +1103,10 @@ def emit_qcd_adjoint(proc, opaque_inputs=True, group_barriers=True, regroup=Fals
                 body.append(f'zb[{i}] = {_adj_lvalue(n)};')
     out += ['    ' + l for l in body]
     out.append('}')
-    per_gconf = 2 * ir.gluon_flops + ag.flops + 2 * (ir.quark_flops + rec_q + ir.colour_flops + 1 + aq.flops)
+    if recompute_currents:
+        per_gconf = 2 * (ir.gluon_flops + ir.quark_flops + rec_q + ir.colour_flops + 1 + aq.flops)
+    else:
+        per_gconf = 2 * ir.gluon_flops + ag.flops + 2 * (ir.quark_flops + rec_q + ir.colour_flops + 1 + aq.flops)
     flops = dict(adjoint_per_event=(2 ** (k - 1)) * per_gconf, kin_slots=len(slots),
                  adjoint_gluon_sweep=ag.flops, adjoint_quark_colour_sweep=aq.flops)
     out.append(f'// flops per event of the adjoint (generated count): {flops}')
@@ -1076,7 +1168,10 @@ SHARE_F32_VALU = False
 # read current adjoints in LDS too (jb_mem; 39.9 KB per wave in FP64, the most that
 # leaves four waves per compute unit): FP64 38.6 -> 33.3 ms, FP32 unchanged (8.25 vs
 # 8.36 ms).  For gg -> ttbar gg, 78 of them (40 KB per wave in FP32) was slower
-# (28.5 -> 29.2 ms), and in FP64 its z slots alone take 42 KB.
+# (28.5 -> 29.2 ms), and in FP64 its z slots alone take 42 KB.  Recomputing the gluon
+# currents per ordering as well (recompute_currents: no current lives across orderings,
+# 40% more flops for gg -> ttbar g) was slower for gg -> ttbar g (FP32 8.3 -> 10.9 ms, FP64
+# 33.5 -> 49.0 ms), and gg -> ttbar gg in that form took over 30 minutes to compile.
 ADJ_OPTS = {
     'gg_tt': dict(zb_mem=True, regroup=True, group_depth=2),
     'gg_ttg': dict(zb_mem=True, regroup=True, group_depth=3, jb_mem=20),

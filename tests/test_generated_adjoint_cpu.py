@@ -121,6 +121,10 @@ CASES = [
     ('gg_ttg', 'double', 2, 8, dict(zb_mem=True, jb_mem=True)),
     ('gg_ttg', 'double', 1, 8, dict(ZB, group_depth=3, jb_mem=20)),
     ('gg_ttgg', 'double', 1, 3, dict(ZB, group_depth=4)),
+    ('gg_tt', 'double', 1, 8, dict(zb_mem=True, recompute_currents=True)),
+    ('gg_ttg', 'double', 1, 16, dict(zb_mem=True, recompute_currents=True)),
+    ('gg_ttg', 'float', 3, 16, dict(zb_mem=True, recompute_currents=True)),
+    ('gg_ttgg', 'double', 1, 3, dict(zb_mem=True, recompute_currents=True)),
     ('gg_ttgg', 'float', 3, 3, dict(ZB, group_depth=2, jb_mem=True)),
 ]
 
