@@ -103,29 +103,30 @@ ZB = dict(zb_mem=True, regroup=True)
 CASES = [
     # (process, working type, tangent directions per kinematic pass, events, emitter options):
     # accumulators in registers or in the caller's memory (zb_mem; jb_mem: the current
-    # adjoints too), quark line swept at once or by groups of orderings sharing their
-    # first group_depth gluons (regroup)
+    # adjoints too, all or the least read ones), quark line swept at once or by groups of
+    # orderings sharing their first group_depth gluons (regroup), or with the gluon currents
+    # recomputed per ordering too (recompute_currents).  gg -> ttbar gg compiles for a
+    # minute, so it runs the register form and the library's form in both precisions only.
     ('gg_tt', 'double', 3, 16, {}),
     ('gg_ttg', 'double', 6, 16, {}),
     ('gg_ttg', 'double', 2, 6, {}),
     ('gg_ttg', 'float', 6, 16, {}),
     ('gg_ttgg', 'double', 3, 3, {}),
-    ('gg_ttgg', 'float', 9, 3, {}),
     ('gg_tt', 'double', 3, 8, RG),
     ('gg_ttg', 'double', 3, 16, RG),
     ('gg_ttg', 'float', 3, 16, RG),
-    ('gg_ttgg', 'double', 3, 3, RG),
     ('gg_tt', 'double', 1, 8, dict(ZB, group_depth=2)),
+    ('gg_tt', 'float', 3, 8, dict(ZB, group_depth=2)),
     ('gg_ttg', 'double', 1, 16, dict(ZB, group_depth=3)),
     ('gg_ttg', 'float', 3, 16, dict(ZB, group_depth=3)),
     ('gg_ttg', 'double', 2, 8, dict(zb_mem=True, jb_mem=True)),
     ('gg_ttg', 'double', 1, 8, dict(ZB, group_depth=3, jb_mem=20)),
+    ('gg_ttg', 'float', 3, 8, dict(ZB, group_depth=3, jb_mem=20)),
     ('gg_ttgg', 'double', 1, 3, dict(ZB, group_depth=4)),
+    ('gg_ttgg', 'float', 3, 3, dict(ZB, group_depth=4)),
     ('gg_tt', 'double', 1, 8, dict(zb_mem=True, recompute_currents=True)),
     ('gg_ttg', 'double', 1, 16, dict(zb_mem=True, recompute_currents=True)),
     ('gg_ttg', 'float', 3, 16, dict(zb_mem=True, recompute_currents=True)),
-    ('gg_ttgg', 'double', 1, 3, dict(zb_mem=True, recompute_currents=True)),
-    ('gg_ttgg', 'float', 3, 3, dict(ZB, group_depth=2, jb_mem=True)),
 ]
 
 
@@ -164,3 +165,10 @@ def test_generated_adjoint_on_cpu_matches_oracle_gradient(tmp_path, proc, rtype,
     else:
         assert np.median(rel_me) < 1e-5 and rel_me.max() < 1e-3
         assert np.median(err) < 1e-4 and err.max() < 1e-2, err
+
+
+def test_the_library_forms_are_among_the_cases():
+    """Each process's derivative form as the library builds it (ADJ_OPTS) runs above in both precisions."""
+    for proc, opts in pc.ADJ_OPTS.items():
+        for rtype in ('double', 'float'):
+            assert any(c[0] == proc and c[1] == rtype and c[4] == opts for c in CASES), (proc, rtype, opts)
