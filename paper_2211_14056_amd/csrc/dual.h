@@ -1,10 +1,10 @@
 // Forward-mode (tangent) arithmetic: Dual<T> = value + eps * tangent, eps^2 = 0.
 //
-// The derivative kernel evaluates the phase space and the generated
-// matrix-element recursion with Dual scalars, one input direction at a time;
-// every operation below is the exact first-order rule of its scalar
-// counterpart, so the tangent of the output is the directional derivative
-// of the same floating-point program.
+// One input direction at a time.  The derivative kernel carries the kinematics
+// through the several-direction form DualN (dualn.h); the phase-space and
+// wavefunction code is written for either.  Every operation below is the exact
+// first-order rule of its scalar counterpart, so the tangent of the output is
+// the directional derivative of the same floating-point program.
 #pragma once
 #include <hip/hip_runtime.h>
 

@@ -4,9 +4,9 @@
 // matrix element from such external-state routines plus vertices and
 // propagators (sect. 2, Fig. 2); it does not print their form.
 //
-// All wavefunctions are evaluated in the kinematic type KT (double, or
-// Dual<double> in the derivative kernel) and rounded once to the kernel's
-// working type R.
+// All wavefunctions are evaluated in the kinematic type KT (double, or the
+// tangent types of dual.h / dualn.h in the derivative kernel) and rounded once
+// to the kernel's working type R.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
