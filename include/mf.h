@@ -218,13 +218,15 @@ mf_status mf_matrix_element(mf_handle h, const mf_request* reqs, int n_reqs, int
  * for the identity, and the phase space) and to (m_t, alpha_s).  The paper's
  * operator has no derivative (sect. 2); this one is a reverse sweep over the
  * helicity/colour recursion that recomputes every helicity's currents instead
- * of storing them, with forward tangents over the d + 1 kinematic inputs (cost
- * about three forward evaluations plus the phase space, whatever d).  The
+ * of storing them, with forward tangents over the d + 1 kinematic inputs (the
+ * sweep's arithmetic is about four forward evaluations, whatever d, plus the
+ * phase space and its tangents).  The
  * forward value is written to me_out when it is not NULL (f64 for MF_FP64,
  * f32 otherwise).  The requests of one process are served by one launch (a
  * grid of 64-event tiles over up to 32 requests); all requests share `edges`.
  * Errors: as mf_matrix_element, plus NULL x / grad_me / grad_x / grad_theta,
- * MF_ERR_UNSUPPORTED for MF_EE_MUMU and MF_GG_TTGGG.
+ * MF_ERR_UNSUPPORTED for MF_EE_MUMU, MF_GG_TTGGG and the quark-initiated
+ * processes.
  */
 mf_status mf_matrix_element_vjp(mf_handle h, const mf_request* reqs, int n_reqs, int precision,
                                 const mf_params* prm, const double* edges, int nb, void* stream);
