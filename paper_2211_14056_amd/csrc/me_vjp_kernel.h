@@ -23,6 +23,7 @@ namespace mf {
 // gg -> ttbar g events (whole derivative): FP32 recursion 8.27 ms with three
 // directions per pass, 8.96 with two, 10.76 with one; FP64 recursion (whose adjoint
 // still spills) 38.5 ms with one direction per pass, 40.4 with two, 42.2 with three.
+// gg -> ttbar gg, FP32, 2^18 events: 28.7 ms with three, 29.0 with two, 35.9 with one.
 template <typename R> constexpr int vjp_tangent_width() { return sizeof(R) == 8 ? 1 : 3; }
 
 // derivative of event e of request q (shared settings in j)
