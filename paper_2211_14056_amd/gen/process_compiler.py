@@ -923,9 +923,16 @@ def emit_qcd_adjoint(proc, opaque_inputs=True, group_barriers=True, regroup=Fals
     zb[i * ZS]; ZS = 64 puts one lane's slots a wavefront apart in LDS) instead of in
     registers.  jb_mem (with zb_mem): the adjoints of the gluon currents the quark line
     reads accumulate there too, after the z slots, and are loaded back for the gluon
-    sweep (True: all of them; a number: that many, the least read ones).  Returns
-    (source, flop counts)."""
+    sweep (True: all of them; a number: that many, the least read ones).
+    recompute_currents: after the colour sums' sweep, each ordering recomputes its gluon
+    currents as well as its quark line and sweeps both (_ordering_sweeps_with_currents), so
+    no current adjoint accumulates across orderings and the gluon sweep after the loop goes.
+    Returns (source, flop counts)."""
     from .adjoint import Adjoint, base_sign, operand_names, defined_names
+    if jb_mem and not zb_mem:
+        raise ValueError('jb_mem puts the current adjoints after the z slots of zb: it needs zb_mem')
+    if recompute_currents and (regroup or jb_mem):
+        raise ValueError('recompute_currents sweeps per ordering by itself: no regroup or jb_mem with it')
     k = proc.k
     ir = _build_ir(proc, 0, False, False, group_barriers)
     b, q, cs = ir.b, ir.q, ir.cs
